@@ -1,0 +1,425 @@
+"""Pins of the FP64 CPU oracle against what the paper and mathematics fix.
+
+None of these compares the oracle with itself: each checks it against an
+identity, a closed form, a special case that reduces to a library routine, or
+a construction done here independently (isotropy tensors by brute-force
+pairing, Hermite tensors by their explicit expansion, the paper's printed
+closed forms typed out again from the paper, the compact K -> infinity forms).
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+from numpy.polynomial import hermite_e
+
+from lbm_analysis import (hermite_explicit, kronecker_delta_tensor, moment_tensor,
+                          sym_perm_delta)
+
+LATS = ["D2Q9", "D3Q19", "D3Q39"]
+RNG = np.random.default_rng(7)
+
+
+def _rand_u(D, scale=0.06):
+    return RNG.uniform(-scale, scale, size=D)
+
+
+def _rand_pi(D, scale=1e-3):
+    A = RNG.uniform(-scale, scale, size=(D, D))
+    return 0.5 * (A + A.T)
+
+
+# --------------------------------------------------------------------------
+# P1: isotropy condition (eq. iso) and the lattice catalogue.
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", LATS)
+def test_isotropy_holds_to_2N(oracle_mod, name):
+    L = oracle_mod.lattice(name)
+    c, w, T0, two_n, D = L["c"], L["w"], L["T0"], L["two_n"], L["D"]
+    assert L["Q"] == {"D2Q9": 9, "D3Q19": 19, "D3Q39": 39}[name]
+    assert two_n == {"D2Q9": 4, "D3Q19": 4, "D3Q39": 6}[name]
+    assert abs(w.sum() - 1.0) < 1e-15
+    for n in range(1, two_n + 2):
+        E = moment_tensor(c, w, n)
+        ref = T0 ** (n / 2) * kronecker_delta_tensor(D, n) if n % 2 == 0 else np.zeros_like(E)
+        assert np.abs(E - ref).max() < 1e-15 * max(1.0, np.abs(ref).max()), (name, n)
+    # ... and fails at the next even order, so 2N is the lattice's order.
+    n = two_n + 2
+    E = moment_tensor(c, w, n)
+    ref = T0 ** (n / 2) * kronecker_delta_tensor(D, n)
+    assert np.abs(E - ref).max() > 1e-3
+
+
+def _shells_of(c):
+    keys = [tuple(sorted(np.abs(ci), reverse=True)) for ci in c]
+    shells = sorted(set(keys))
+    return shells, keys
+
+
+@pytest.mark.parametrize("name", LATS)
+def test_weights_and_T0_solve_the_isotropy_system(oracle_mod, name):
+    """Re-derive (w, T0) from eq. iso: the shell weights enter linearly and the
+    right-hand sides are powers of T0; the system is consistent only where the
+    determinant of the augmented matrix vanishes, a polynomial in T0."""
+    L = oracle_mod.lattice(name)
+    c, D, two_n = L["c"].astype(float), L["D"], L["two_n"]
+    shells, keys = _shells_of(L["c"])
+    # independent scalar conditions: sum w = 1, and even moments component-wise
+    conds = [((), 0)]
+    comps = {2: [(2,)], 4: [(4,), (2, 2)], 6: [(6,), (4, 2), (2, 2, 2)]}
+    for n in range(2, two_n + 1, 2):
+        for pat in comps[n]:
+            if len(pat) > D:
+                continue
+            conds.append((pat, n))
+    A = np.zeros((len(conds), len(shells)))
+    for r, (pat, n) in enumerate(conds):
+        for s, sh in enumerate(shells):
+            tot = 0.0
+            for ci, k in zip(c, keys):
+                if k != sh:
+                    continue
+                tot += math.prod(ci[a] ** p for a, p in enumerate(pat))
+            A[r, s] = tot
+    # rhs: T0^(n/2) times the number of pairings of that component pattern
+    def rhs(T0):
+        out = []
+        for pat, n in conds:
+            cnt = math.prod(math.factorial(p) // (2 ** (p // 2) * math.factorial(p // 2)) for p in pat)
+            out.append(T0 ** (n // 2) * cnt)
+        return np.array(out)
+
+    if A.shape[0] == A.shape[1] + 1:
+        # determinant is a polynomial in T0 of degree <= two_n / 2: fit it exactly
+        deg = two_n // 2
+        ts = np.linspace(0.1, 1.5, deg + 1)
+        dets = [np.linalg.det(np.column_stack([A, rhs(t)])) for t in ts]
+        roots = np.roots(np.polyfit(ts, dets, deg))
+        # T0 = 0 is the trivial root (all weight on the rest particle)
+        real = sorted(r.real for r in roots if abs(r.imag) < 1e-9 and r.real > 1e-6)
+        sols = []
+        for T0 in real:
+            wsh, *_ = np.linalg.lstsq(A, rhs(T0), rcond=None)
+            if np.all(wsh > 0):
+                sols.append((T0, wsh))
+        assert len(sols) == 1, sols
+        T0, wsh = sols[0]
+    else:
+        T0 = L["T0"]
+        wsh, res, *_ = np.linalg.lstsq(A, rhs(T0), rcond=None)
+    assert abs(T0 - L["T0"]) < 1e-12
+    for ci, k, wi in zip(c, keys, L["w"]):
+        assert abs(wsh[shells.index(k)] - wi) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# P2 / P7: Hermite tensors.
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", LATS)
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 4])
+def test_hermite_tensors_match_explicit_expansion(oracle_mod, name, n):
+    L = oracle_mod.lattice(name)
+    H = oracle_mod.hermite(name, n)
+    xi = L["c"] / math.sqrt(L["T0"])
+    for i in range(L["Q"]):
+        assert np.abs(H[i] - hermite_explicit(xi[i], n)).max() < 1e-12
+
+
+@pytest.mark.parametrize("name", LATS)
+def test_hermite_orthogonality(oracle_mod, name):
+    """sum_i w_i H^(n)_i H^(m)_i = delta_nm (sum of permutation deltas), valid
+    while n + m <= 2N + 1; fails beyond (D3Q19: (2,4), (3,3); D3Q39: (4,4))."""
+    L = oracle_mod.lattice(name)
+    w, D, two_n = L["w"], L["D"], L["two_n"]
+    Hs = {n: oracle_mod.hermite(name, n) for n in range(0, 5)}
+    for n in range(0, 5):
+        for m in range(0, 5):
+            G = np.einsum("i...,i->...", np.einsum("i...,i...->i...",
+                          Hs[n].reshape((L["Q"],) + (D,) * n + (1,) * m),
+                          Hs[m].reshape((L["Q"],) + (1,) * n + (D,) * m)), w)
+            ref = sym_perm_delta(D, n) if n == m else np.zeros(G.shape)
+            err = np.abs(G - ref).max()
+            if n + m <= two_n + 1:
+                assert err < 1e-13, (name, n, m, err)
+    bad = {"D3Q19": [(2, 4), (3, 3), (4, 4)], "D3Q39": [(4, 4)], "D2Q9": [(3, 3)]}[name]
+    for n, m in bad:
+        G = np.einsum("i...,i->...", np.einsum("i...,i...->i...",
+                      Hs[n].reshape((L["Q"],) + (D,) * n + (1,) * m),
+                      Hs[m].reshape((L["Q"],) + (1,) * n + (D,) * m)), w)
+        ref = sym_perm_delta(D, n) if n == m else np.zeros(G.shape)
+        assert np.abs(G - ref).max() > 1e-3, (name, n, m)
+
+
+def test_third_order_hermite_vanishes_on_2N4_nodes(oracle_mod):
+    for name in ["D2Q9", "D3Q19"]:
+        H3 = oracle_mod.hermite(name, 3)
+        assert np.abs(H3[:, 0, 0, 0]).max() < 1e-14
+    assert np.abs(oracle_mod.hermite("D3Q19", 3)[:, 0, 1, 2]).max() < 1e-14
+
+
+@pytest.mark.parametrize("name", LATS)
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 4, 5])
+def test_hermite_contraction_is_scalar_hermite(oracle_mod, name, n):
+    """P7: H^(n)(xi) . V^[n] = |V|^n He_n(xi . V / |V|) (numpy's HermiteE)."""
+    L = oracle_mod.lattice(name)
+    D = L["D"]
+    H = oracle_mod.hermite(name, n)
+    xi = L["c"] / math.sqrt(L["T0"])
+    V = _rand_u(D, 0.3)
+    Vn = np.array(1.0)
+    for _ in range(n):
+        Vn = np.multiply.outer(Vn, V)
+    lhs = np.array([np.sum(H[i] * Vn) for i in range(L["Q"])])
+    nv = np.linalg.norm(V)
+    coef = np.zeros(n + 1)
+    coef[n] = 1.0
+    rhs = nv ** n * hermite_e.hermeval(xi @ V / nv, coef)
+    assert np.abs(lhs - rhs).max() < 1e-14
+
+
+# --------------------------------------------------------------------------
+# P3 / P4: exact low moments of the truncated expansions.
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", LATS)
+@pytest.mark.parametrize("mode", ["literal", "closed"])
+def test_feq_moments_exact(oracle_mod, name, mode):
+    L = oracle_mod.lattice(name)
+    c, D, T0 = L["c"].astype(float), L["D"], L["T0"]
+    for K in range(2, L["two_n"]):
+        for _ in range(5):
+            rho = RNG.uniform(0.8, 1.2)
+            u = _rand_u(D, 0.12)
+            f = oracle_mod.feq(name, K, rho, u, mode=mode)
+            assert abs(f.sum() - rho) < 2e-15
+            assert np.abs(c.T @ f - rho * u).max() < 2e-15
+            M2 = np.einsum("ia,ib,i->ab", c, c, f)
+            assert np.abs(M2 - rho * (np.outer(u, u) + T0 * np.eye(D))).max() < 2e-15
+
+
+@pytest.mark.parametrize("name", LATS)
+@pytest.mark.parametrize("mode", ["literal", "closed"])
+def test_filtered_neq_moments_exact(oracle_mod, name, mode):
+    """Sum fhat = 0, sum c fhat = 0, sum c c fhat = Pi for 2 <= K <= 2N-1
+    (the section on Galilean invariance: same momentum flux as the full form)."""
+    L = oracle_mod.lattice(name)
+    c, D = L["c"].astype(float), L["D"]
+    kmax = L["two_n"] - 1 if mode == "literal" else min(4, L["two_n"] - 1)
+    for K in range(2, kmax + 1):
+        for _ in range(5):
+            u = _rand_u(D, 0.12)
+            Pi = _rand_pi(D)
+            f = oracle_mod.fneq(name, K, u, Pi, mode=mode)
+            assert abs(f.sum()) < 1e-18
+            assert np.abs(c.T @ f).max() < 1e-18
+            assert np.abs(np.einsum("ia,ib,i->ab", c, c, f) - Pi).max() < 1e-18
+
+
+def test_truncation_beyond_2N_minus_1_breaks_momentum_flux(oracle_mod):
+    """K = 2N on a 2N = 4 lattice no longer reproduces Pi: the truncation rule
+    of the paper is what keeps the momentum flux exact."""
+    L = oracle_mod.lattice("D3Q19")
+    c = L["c"].astype(float)
+    u = np.array([0.1, 0.05, -0.03])
+    Pi = _rand_pi(3, 1e-2)
+    f = oracle_mod.fneq("D3Q19", 4, u, Pi)
+    assert np.abs(np.einsum("ia,ib,i->ab", c, c, f) - Pi).max() > 1e-6
+
+
+# --------------------------------------------------------------------------
+# P5: the tensor path equals the paper's printed closed forms.
+# --------------------------------------------------------------------------
+
+def _printed_closed_form(L, K, u, Pi):
+    """eq. filter-Pi (K=2), eq. filter-1st (K=3), eq. filter-2nd (K=4), typed
+    again here from the paper, in dyadic form with numpy."""
+    c, w, T0, D = L["c"].astype(float), L["w"], L["T0"], L["D"]
+    I = np.eye(D)
+    out = np.zeros(L["Q"])
+    for i in range(L["Q"]):
+        ci = c[i]
+        ccI = np.outer(ci, ci) / T0 - I
+        cu = ci @ u
+        sym = (np.outer(ci, u) + np.outer(u, ci)) / T0
+        if K == 2:
+            T = ccI
+        elif K == 3:
+            T = (1 + cu / T0) * ccI - sym
+        else:
+            T = ((1 + cu / T0 + cu * cu / (2 * T0 * T0) - (u @ u) / (2 * T0)) * ccI
+                 - (1 + cu / T0) * sym + np.outer(u, u) / T0)
+        out[i] = w[i] / (2 * T0) * np.sum(T * Pi)
+    return out
+
+
+@pytest.mark.parametrize("name,K", [("D2Q9", 2), ("D2Q9", 3), ("D3Q19", 2), ("D3Q19", 3),
+                                    ("D3Q39", 2), ("D3Q39", 3), ("D3Q39", 4)])
+def test_tensor_path_equals_printed_closed_forms(oracle_mod, name, K):
+    L = oracle_mod.lattice(name)
+    for _ in range(10):
+        u = _rand_u(L["D"], 0.15)
+        Pi = _rand_pi(L["D"])
+        ref = _printed_closed_form(L, K, u, Pi)
+        for mode in ["literal", "closed"]:
+            got = oracle_mod.fneq(name, K, u, Pi, mode=mode)
+            assert np.abs(got - ref).max() < 1e-18, (mode, np.abs(got - ref).max())
+
+
+# --------------------------------------------------------------------------
+# P6: K -> infinity limits are the compact forms eq. feq_full, eq. filter-coll.
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", LATS)
+def test_large_K_reaches_compact_forms(oracle_mod, name):
+    L = oracle_mod.lattice(name)
+    c, w, T0, D = L["c"].astype(float), L["w"], L["T0"], L["D"]
+    rho = 1.07
+    u = np.array([0.02, -0.015, 0.01])[:D]
+    Pi = _rand_pi(D, 1e-3)
+    cp = c - u
+    feq_full = w * np.exp((c * c).sum(1) / (2 * T0)) * rho * np.exp(-(cp * cp).sum(1) / (2 * T0))
+    fneq_full = np.array([feq_full[i] / (2 * rho * T0) *
+                          np.sum((np.outer(cp[i], cp[i]) / T0 - np.eye(D)) * Pi) for i in range(L["Q"])])
+    # remainder of the series after order K is O(|xi.V|^(K+1) / (K+1)!) ~ 1e-13 here
+    K = 10
+    assert np.abs(oracle_mod.feq(name, K, rho, u) - feq_full).max() < 1e-12 * np.abs(feq_full).max()
+    assert np.abs(oracle_mod.fneq(name, K, u, Pi) - fneq_full).max() < 1e-12 * np.abs(fneq_full).max()
+    # the low truncations differ from the compact form at the expected order
+    assert np.abs(oracle_mod.fneq(name, 2, u, Pi) - fneq_full).max() > 1e-7
+
+
+# --------------------------------------------------------------------------
+# P8 / P9: u = 0 reduction, collision fixed points.
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", LATS)
+def test_zero_velocity_reduces_to_old_filter(oracle_mod, name):
+    L = oracle_mod.lattice(name)
+    D = L["D"]
+    Pi = _rand_pi(D)
+    ref = _printed_closed_form(L, 2, np.zeros(D), Pi)
+    for K in range(2, L["two_n"]):
+        assert np.abs(oracle_mod.fneq(name, K, np.zeros(D), Pi) - ref).max() < 1e-19
+        assert np.abs(oracle_mod.feq(name, K, 1.3, np.zeros(D)) - 1.3 * L["w"]).max() < 1e-15
+
+
+@pytest.mark.parametrize("name", LATS)
+@pytest.mark.parametrize("kind", ["filtered", "bgk"])
+def test_equilibrium_is_collision_fixed_point(oracle_mod, name, kind):
+    L = oracle_mod.lattice(name)
+    K = oracle_mod.DEFAULT_K[name]
+    f = oracle_mod.feq(name, K, 0.97, _rand_u(L["D"], 0.1))
+    out = oracle_mod.collide(name, f, tau=0.6, K=K, kind=kind)
+    assert np.abs(out - f).max() < 1e-15
+
+
+@pytest.mark.parametrize("name", LATS)
+def test_collision_conserves_and_relaxes_pi(oracle_mod, name):
+    """Post-collision: same rho and rho u (eq. inv), and the non-equilibrium
+    momentum flux scaled by exactly (1 - 1/tau) (eq. post-1 with the flux
+    preserved by the truncation)."""
+    L = oracle_mod.lattice(name)
+    c, D, T0 = L["c"].astype(float), L["D"], L["T0"]
+    K = oracle_mod.DEFAULT_K[name]
+    tau = 0.7
+    f = oracle_mod.feq(name, K, 1.02, _rand_u(D, 0.08)) * (1 + RNG.uniform(-0.02, 0.02, L["Q"]))
+    rho, j = f.sum(), c.T @ f
+    u = j / rho
+    Pi_in = np.einsum("ia,ib,i->ab", c, c, f) - rho * (np.outer(u, u) + T0 * np.eye(D))
+    out = oracle_mod.collide(name, f, tau=tau)
+    assert abs(out.sum() - rho) < 1e-15
+    assert np.abs(c.T @ out - j).max() < 1e-15
+    Pi_out = np.einsum("ia,ib,i->ab", c, c, out) - rho * (np.outer(u, u) + T0 * np.eye(D))
+    assert np.abs(Pi_out - (1 - 1 / tau) * Pi_in).max() < 1e-15
+
+
+# --------------------------------------------------------------------------
+# Streaming half of eq. lbe, uniform flow, dimensional reduction.
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name,dims", [("D2Q9", (5, 4, 1)), ("D3Q19", (4, 3, 5)), ("D3Q39", (7, 2, 3)),
+                                       ("D3Q39", (2, 1, 1))])
+def test_streaming_moves_population_along_its_velocity(oracle_mod, name, dims):
+    """With collision switched off, f_i(x + c_i, t + 1) = f_i(x, t) (eq. lbe),
+    periodic in every direction, including boxes shorter than |c|."""
+    L = oracle_mod.lattice(name)
+    nx, ny, nz = dims
+    sim = oracle_mod.Sim(name, dims, 1.0, kind="none")
+    f0 = RNG.uniform(size=(nz, ny, nx, L["Q"]))
+    sim.set_populations(f0)
+    sim.step(1)
+    f1 = sim.populations()
+    cz = L["c"][:, 2] if L["D"] == 3 else np.zeros(L["Q"], dtype=int)
+    for i in range(L["Q"]):
+        moved = np.roll(f0[..., i], shift=(cz[i], L["c"][i, 1], L["c"][i, 0]), axis=(0, 1, 2))
+        assert np.array_equal(f1[..., i], moved)
+
+
+@pytest.mark.parametrize("name", LATS)
+def test_uniform_flow_is_invariant(oracle_mod, name):
+    L = oracle_mod.lattice(name)
+    D = L["D"]
+    dims = (5, 4, 1) if D == 2 else (4, 3, 5)
+    U = np.array([0.08, -0.05, 0.03])[:D]
+    sim = oracle_mod.Sim(name, dims, 0.6)
+    shape = sim.shape
+    sim.init(np.full(shape, 1.01), np.broadcast_to(U.reshape((D,) + (1,) * 3), (D,) + shape))
+    f0 = sim.populations()
+    sim.step(7)
+    assert np.abs(sim.populations() - f0).max() < 1e-15
+
+
+@pytest.mark.parametrize("name", ["D3Q19", "D3Q39"])
+def test_x_only_field_equals_one_dimensional_run(oracle_mod, name):
+    """A field that depends on x only stays x-only in a 3-D box, and equals the
+    run on an nx x 1 x 1 box bit for bit (the basis of the quasi-1-D parity runs)."""
+    nx = 12
+    ux = RNG.uniform(-0.05, 0.05, size=(3, nx))
+    rx = 1 + RNG.uniform(-0.01, 0.01, size=nx)
+    big = oracle_mod.Sim(name, (nx, 3, 4), 0.55)
+    big.init(np.broadcast_to(rx, big.shape), np.broadcast_to(ux[:, None, None, :], (3,) + big.shape))
+    small = oracle_mod.Sim(name, (nx, 1, 1), 0.55)
+    small.init(rx.reshape(1, 1, nx), ux.reshape(3, 1, 1, nx))
+    big.step(15)
+    small.step(15)
+    rb, ub = big.moments()
+    rs, us = small.moments()
+    assert np.array_equal(rb, np.broadcast_to(rs, rb.shape))
+    assert np.array_equal(ub, np.broadcast_to(us, ub.shape))
+
+
+@pytest.mark.parametrize("name", LATS)
+def test_global_conservation(oracle_mod, name):
+    """P10: total mass and momentum are conserved (eq. conserv) to round-off."""
+    L = oracle_mod.lattice(name)
+    D = L["D"]
+    dims = (16, 16, 1) if D == 2 else (8, 6, 5)
+    sim = oracle_mod.Sim(name, dims, 0.53)
+    shape = sim.shape
+    u = RNG.uniform(-0.05, 0.05, size=(D,) + shape)
+    rho = 1 + RNG.uniform(-0.02, 0.02, size=shape)
+    sim.init(rho, u)
+    t0 = sim.totals()
+    f = sim.populations()
+    assert abs(t0[0] - f.sum()) < 1e-12
+    assert np.abs(t0[1:1 + D] - np.einsum("zyxi,ia->a", f, L["c"].astype(float))).max() < 1e-12
+    sim.step(100)
+    t1 = sim.totals()
+    assert abs(t1[0] - t0[0]) / t0[0] < 1e-13
+    assert np.abs(t1[1:] - t0[1:]).max() / t0[0] < 1e-13
+
+
+def test_literal_and_closed_modes_agree_over_steps(oracle_mod):
+    from paper_2002_02503_amd import inputs
+    for name, dims in [("D3Q19", (6, 5, 4)), ("D3Q39", (7, 4, 3))]:
+        L = oracle_mod.lattice(name)
+        sims = [oracle_mod.Sim(name, dims, 0.58, mode=m) for m in ["literal", "closed"]]
+        shape = sims[0].shape
+        u = RNG.uniform(-0.05, 0.05, size=(3,) + shape)
+        for s in sims:
+            s.init(np.ones(shape), u)
+            s.step(20)
+        assert np.abs(sims[0].populations() - sims[1].populations()).max() < 1e-15
+    del inputs
