@@ -1,0 +1,242 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused stream + filtered-collision step on one MI355X.
+
+Workload (the headline): D3Q19, 256^3 periodic box, tau = 0.51, decaying
+turbulence from a seeded random-phase field (k0 = 4, u_rms = 0.04), FP32
+storage; FP16 and BF16 storage of the deviations, the batched form (256 boxes)
+and D3Q39 (192^3) are reported beside it.  A "step" is one application of the
+lattice Boltzmann equation to every site.  Inputs are resident in HBM before
+the timed region; the timed region is K steps issued as captured graphs,
+bracketed by device synchronisation, timed with HIP events on the stream the
+kernels run on.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS & % HBM roofline, D3Q19 256³ FP32 vs FP16-storage at stated error"
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E peak
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_d3q19_256_fp32.json")
+KERNEL_SOURCES = ["lattice.hpp", "collide.hpp", "kernels.hip"]
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def source_hash() -> str:
+    """Hash of the kernel sources, to tell whether stored counters still apply."""
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2002_02503_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def timed_steps(sim, steps: int, warmup: int) -> float:
+    """Milliseconds per step over `steps` steps after `warmup` untimed ones."""
+    import torch
+
+    sim.prepare()
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    sim.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def measure_box(lattice, dims, tau, dtype, rho, u, steps, warmup, **kw):
+    from paper_2002_02503_amd import lbm
+
+    with lbm.Simulation(lattice, dims, tau, dtype=dtype, **kw) as sim:
+        sim.init(rho, u)
+        ms = timed_steps(sim, steps, warmup)
+        info = sim.info()
+    bytes_site = info["bytes_per_site_update"]
+    nsites = info["nsites"]
+    mlups = nsites / (ms * 1e-3) / 1e6
+    gbs = bytes_site * nsites / (ms * 1e-3) / 1e9
+    return {"value": mlups, "unit": "MLUPS", "ms_per_step": ms, "steps": steps,
+            "bytes_per_site_update": bytes_site, "nsites": nsites, "achieved_GBs": gbs,
+            "roofline_frac": gbs / PEAK_HBM_GBS, "block": info["block"]}
+
+
+def traffic_per_launch():
+    """HBM bytes per launch of the FP32 256^3 step from the committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel
+    calibration), or None when absent or taken on other kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None, "no counter summary"
+    with open(TRAFFIC_FILE) as f:
+        t = json.load(f)
+    if t.get("source_hash") != source_hash():
+        return None, "kernel changed since the counters were taken"
+    return float(t["traffic_bytes_per_launch"]), "rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-calibrated"
+
+
+def cpu_baseline_leg(rho, u, tau, budget_s: float, dtypes):
+    """The FP64 oracle as it stands, on the full 256^3 box, for as many steps as
+    fit in about `budget_s` seconds of host time -- timed as the CPU baseline.
+    Its fields after those steps, and a 500-step oracle run of the same recipe
+    at 32^3, are the references for the error statement of every storage type
+    (max and L2 error of u and rho)."""
+    import numpy as np
+
+    import oracle
+    from paper_2002_02503_amd import inputs, lbm
+
+    def errs(r, uu, r_ref, u_ref):
+        du, dr = uu - u_ref, r - r_ref
+        return {"u_max_rel": float(np.abs(du).max() / np.abs(u_ref).max()),
+                "u_l2_rel": float(np.sqrt(np.sum(du * du) / np.sum(u_ref * u_ref))),
+                "rho_max": float(np.abs(dr).max()),
+                "rho_l2_rel": float(np.sqrt(np.sum(dr * dr) / np.sum(r_ref * r_ref)))}
+
+    t0 = time.perf_counter()
+    sim = oracle.Sim("D3Q19", (256, 256, 256), tau)
+    sim.init(rho, u)
+    t_init = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    sim.step(1)
+    one = time.perf_counter() - t1
+    extra = max(0, min(19, int(budget_s / max(one, 1e-3)) - 1))
+    t2 = time.perf_counter()
+    sim.step(extra)
+    steps = 1 + extra
+    wall = one + (time.perf_counter() - t2)
+    nsites = 256 ** 3
+    base = {"value": nsites * steps / wall / 1e6, "unit": "MLUPS", "cores": oracle.get_threads(), "kind": "oracle",
+            "sample": f"{steps} step(s) of the full 256^3 D3Q19 turbulence box, FP64 oracle "
+                      f"(literal Hermite-tensor mode, OpenMP), {wall:.1f} s stepping + {t_init:.1f} s init"}
+    r_ref, u_ref = sim.moments()
+    del sim
+    errors = {}
+    for dt in dtypes:
+        log(f"error statement {dt}: 256^3 after {steps} steps")
+        with lbm.Simulation("D3Q19", (256, 256, 256), tau, dtype=dt) as g:
+            g.init(rho, u).step(steps)
+            r, uu = g.moments()
+        errors[dt] = {f"full_256cubed_{steps}_steps": errs(r, uu, r_ref, u_ref)}
+        del r, uu
+    del r_ref, u_ref
+    log("error statement: 32^3 same recipe, 500 steps")
+    srho, su = inputs.turbulence(32)
+    ref = oracle.Sim("D3Q19", (32, 32, 32), tau).init(srho, su).step(500)
+    r_ref, u_ref = ref.moments()
+    for dt in dtypes:
+        with lbm.Simulation("D3Q19", (32, 32, 32), tau, dtype=dt) as g:
+            g.init(srho, su).step(500)
+            r, uu = g.moments()
+        errors[dt]["recipe_32cubed_500_steps"] = errs(r, uu, r_ref, u_ref)
+    return base, errors
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-variants", action="store_true", help="headline FP32 measurement only")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle leg (CPU baseline timing and error statements)")
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle stepping")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the slab decomposition over xGMI is a design, not code). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2002_02503_amd import inputs, lbm
+
+    torch.cuda.set_device(0)
+    lbm.load_library()
+    tau = 0.51
+    log("generating the 256^3 turbulence field")
+    rho, u = inputs.turbulence(256)
+
+    log(f"FP32 256^3: {args.warmup} warm-up + {args.steps} timed steps")
+    head = measure_box("D3Q19", (256, 256, 256), tau, "fp32", rho, u, args.steps, args.warmup)
+    nsites = head["nsites"]
+    traffic, traffic_src = traffic_per_launch()
+    roofline = {"bound": "hbm", "achieved": head["achieved_GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": head["achieved_GBs"] / PEAK_HBM_GBS, "traffic": traffic,
+                "algorithmic_bytes_per_launch": head["bytes_per_site_update"] * nsites,
+                "kernel": "k_step<D3Q19, float, K=3>", "traffic_source": traffic_src}
+
+    log("copy probe at the same footprint")
+    copy_bytes = head["bytes_per_site_update"] // 2 * nsites
+    copy_ms = lbm.copy_probe(copy_bytes, reps=10)
+    copy_gbs = 2 * copy_bytes / (copy_ms * 1e-3) / 1e9
+
+    variants = {}
+    if not args.no_variants:
+        for dt in ["fp16", "bf16"]:
+            log(f"{dt} storage 256^3")
+            variants[dt] = measure_box("D3Q19", (256, 256, 256), tau, dt, rho, u, args.steps, args.warmup)
+        log("batched: 256 D3Q19 boxes, 1000 steps")
+        boxes = inputs.batch_boxes()
+        fields = [inputs.taylor_green_box(b["dims"], b["U"], 1.0 / 3.0) for b in boxes]
+        brho = np.concatenate([f[0].ravel() for f in fields])
+        bu = np.concatenate([f[1].reshape(3, -1) for f in fields], axis=1)
+        variants["batched_fp32"] = measure_box("D3Q19", [b["dims"] for b in boxes], [b["tau"] for b in boxes],
+                                               "fp32", brho, bu, 1000, args.warmup)
+        variants["batched_fp32"]["config"] = "256 boxes, sides 16..64, tau 0.52..1, |U| <= 0.1, Taylor-Green"
+        del brho, bu, fields
+        log("D3Q39 192^3 FP32, 1000 steps")
+        srho, su = inputs.shear_wave((192, 192, 192), 0.01, (0.2, 0.0, 0.0))
+        variants["d3q39_fp32_192"] = measure_box("D3Q39", (192, 192, 192), 0.6, "fp32", srho, su, 1000,
+                                                 args.warmup)
+        del srho, su
+
+    cpu, errors = None, {}
+    if not args.no_cpu_baseline:
+        log("CPU baseline leg: FP64 oracle on the host cores, and the error statements")
+        dts = ["fp32", "fp16", "bf16"] if not args.no_variants else ["fp32"]
+        cpu, errors = cpu_baseline_leg(rho, u, tau, args.cpu_budget, dts)
+
+    line = {
+        "metric": METRIC,
+        "value": head["value"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "D3Q19 256^3 periodic, decaying turbulence (k0=4, u_rms=0.04, seeded), "
+                               "tau=0.51, FP32 storage of S(f_i - w_i), Hermite order 3",
+                   "lattice": "D3Q19", "dims": [256, 256, 256], "tau": tau, "hermite_order": 3},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "copy_probe": {"bytes_moved": 2 * copy_bytes, "GB_s": copy_gbs, "frac_of_peak": copy_gbs / PEAK_HBM_GBS},
+        "frac_of_copy": head["achieved_GBs"] / copy_gbs,
+        "variants": variants,
+        "errors": errors,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,192 @@
+/*
+ * lbm.h -- C ABI of the MI355X lattice Boltzmann library (liblbm.so).
+ *
+ * The library advances a distribution f_i(x, t) on a periodic D-dimensional
+ * lattice with the lattice Boltzmann equation in lattice units (dx = dt = 1):
+ *
+ *     f_i(x + c_i, t + 1) = f^eq_i(x, t) + (1 - 1/tau) fhat^neq_i(x, t)
+ *
+ * (eq. lbe in the introduction, in its regularised form eq. lbe-reg), where
+ * the equilibrium is the Hermite expansion eq. hermite and the filtered
+ * non-equilibrium part is the Galilean-invariant expansion eq. hermite-coll,
+ * both truncated at Hermite order K (default: 3 on D2Q9 and D3Q19, whose
+ * isotropy order is 2N = 4, giving eq. filter-1st; 4 on D3Q39, 2N = 6, giving
+ * eq. filter-2nd).  rho and u are the zeroth and first moments (eq. mme) and
+ * Pi^neq the non-equilibrium momentum flux (eq. coeff-2 / eq. Pi_def).
+ *
+ * Conventions for every call:
+ *   - Return value: lbm_status; LBM_OK (0) on success, a negative code on
+ *     failure.  No C++ exception crosses the ABI.  lbm_last_error() gives a
+ *     thread-local message for the most recent failure on that thread.
+ *   - Arguments are validated on the host before any device work, so a call
+ *     that returns LBM_EINVAL or LBM_ESTATE has changed nothing.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ *   - Field layout: rho is [nz][ny][nx] (x fastest) float64; u is
+ *     [D][nz][ny][nx] float64 (component-major).  A batch concatenates its
+ *     boxes in creation order, each in that layout (rho: all boxes' sites;
+ *     u: component a of every box is the a-th block of total-site length).
+ *   - Device work runs on the handle's stream (lbm_set_stream); calls that
+ *     return host data synchronise that stream.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx* lbm_t;
+
+/* Velocity sets.  D2Q9 and D3Q19: T0 = 1/3, 2N = 4.  D3Q39: T0 = 2/3, 2N = 6
+ * (eq. iso and the lattice catalogue that follows it). */
+typedef enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1, LBM_D3Q39 = 2 } lbm_lattice;
+
+/* Storage type of the populations.  All types store the deviation
+ * g_i = f_i - w_i.  Arithmetic: FP64 computes in double; FP32, FP16 and BF16
+ * compute per population in float, with the moment sums and the conservation
+ * correction accumulated in double. */
+typedef enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16 = 2, LBM_BF16 = 3 } lbm_dtype;
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,   /* bad argument (tau <= 1/2, bad dims, unknown enum, NULL pointer, ...) */
+    LBM_ENOMEM = -2,   /* device or host allocation failed */
+    LBM_EDEVICE = -3,  /* a HIP runtime call or kernel launch failed */
+    LBM_ENODEV = -4,   /* no usable GPU */
+    LBM_ESTATE = -5,   /* call not valid in the current state (e.g. step before init) */
+    LBM_ENUMERIC = -6  /* non-finite or non-positive density found by lbm_totals */
+} lbm_status;
+
+typedef struct {
+    int32_t lattice, dtype;
+    int32_t D, Q, two_n, K;      /* dimension, velocities, isotropy order, Hermite truncation */
+    double T0;                   /* lattice temperature c_s^2 */
+    int32_t nbox;                /* 1 for a single box */
+    int64_t dims[3];             /* box 0 (nx, ny, nz) */
+    int64_t nsites;              /* total sites over all boxes */
+    int64_t t;                   /* steps taken since lbm_init */
+    int64_t bytes_per_site_update; /* 2 * Q * sizeof(storage): one read + one write per population */
+    uint64_t state_bytes;        /* bytes of one population buffer (see lbm_state_bytes) */
+    int32_t block, grid;         /* launch shape in use (threads per block; batched grid size, 0 = one block per tile) */
+    int32_t graph_chunk;         /* steps per captured graph */
+} lbm_info;
+
+/* Create a single periodic box (eq. lbe on an nx*ny*nz torus).
+ * dims = {nx, ny, nz}, each >= 1; D2Q9 requires nz == 1.  Each of nx, ny, nz
+ * and the total number of sites must be below 2^31.  tau: relaxation time,
+ * finite and > 1/2 (viscosity T0 (tau - 1/2)).  No device memory for the
+ * populations is allocated until lbm_init / lbm_set_state, unless bound with
+ * lbm_bind_state.  Errors: LBM_EINVAL, LBM_ENODEV, LBM_EDEVICE, LBM_ENOMEM. */
+lbm_status lbm_create(lbm_t* out, int32_t lattice, const int64_t dims[3], double tau, int32_t dtype);
+
+/* Create nbox independent periodic boxes advanced together by one launch per
+ * step.  dims: nbox * 3 int64 (nx, ny, nz per box); tau: nbox doubles.  Same
+ * rules per box as lbm_create.  Boxes are stored back to back, in order. */
+lbm_status lbm_create_batch(lbm_t* out, int32_t lattice, int32_t nbox, const int64_t* dims,
+                            const double* tau, int32_t dtype);
+
+/* Hermite truncation order K of both expansions, 2 <= K <= 2N - 1 (the
+ * truncation rule after eq. hermite-coll).  K = 2 is the zero-velocity filter
+ * eq. filter-Pi with the second-order equilibrium.  Only before lbm_init. */
+lbm_status lbm_set_hermite_order(lbm_t h, int32_t K);
+
+/* Run device work on `hip_stream` (a hipStream_t; NULL = the null stream).
+ * The caller keeps ownership of the stream; it must outlive the handle's use. */
+lbm_status lbm_set_stream(lbm_t h, void* hip_stream);
+
+/* Bytes needed for one population buffer (Q planes, each padded to 256 bytes). */
+lbm_status lbm_state_bytes(lbm_t h, size_t* bytes_each);
+
+/* Use caller-owned device memory (e.g. two torch tensors) for the two
+ * population buffers instead of library allocations.  Each must hold at least
+ * lbm_state_bytes() bytes, be 256-byte aligned, live on the handle's device and
+ * outlive the handle.  Only before lbm_init / lbm_set_state. */
+lbm_status lbm_bind_state(lbm_t h, void* buf_a, void* buf_b, size_t bytes_each);
+
+/* f := f^eq_K(rho, u) at every site (eq. hermite), t := 0.  rho and u are
+ * float64 in the field layout above; on_device != 0 means they are device
+ * pointers, else host pointers (copied, then released).  Borrowed for the
+ * call only; synchronises the stream. */
+lbm_status lbm_init(lbm_t h, const double* rho, const double* u, int32_t on_device);
+
+/* Advance n >= 0 steps of eq. lbe-reg: per site pull f_i from x - c_i
+ * (periodic), collide, store.  Asynchronous on the handle's stream; long runs
+ * are issued as captured graphs of graph_chunk steps.  LBM_ESTATE before init. */
+lbm_status lbm_step(lbm_t h, int64_t n);
+
+/* Build (or rebuild) the captured step graphs now, so that a later lbm_step
+ * does not pay for graph instantiation.  Optional. */
+lbm_status lbm_prepare(lbm_t h);
+
+/* Steps per captured graph (>= 1; default 32).  Takes effect at the next
+ * lbm_step / lbm_prepare. */
+lbm_status lbm_set_graph_chunk(lbm_t h, int32_t steps);
+
+/* Launch shape: threads per block (64, 128 or 256; 0 = default) and,
+ * for batches, the number of blocks of the persistent step kernel (0 = one
+ * block per tile).  Only before lbm_init. */
+lbm_status lbm_set_launch(lbm_t h, int32_t block, int32_t grid);
+
+/* rho and u (eq. mme) of the current state, in float64, in the field layout
+ * above.  on_device: as for lbm_init.  Synchronises. */
+lbm_status lbm_moments(lbm_t h, double* rho, double* u, int32_t on_device);
+
+/* Global totals per box, float64, computed on the GPU with a fixed reduction
+ * order: out[4*b + 0] = sum rho, out[4*b + 1 + a] = sum rho u_a (a < 3; 0 for
+ * a >= D).  out has 4 * nbox doubles on the host.  Returns LBM_ENUMERIC when a
+ * total is not finite or a box's mass is not positive.  Synchronises. */
+lbm_status lbm_totals(lbm_t h, double* out);
+
+/* Error residuals of the current state against reference fields (same layout
+ * as lbm_moments), in float64 on the GPU: out = {max |du|, sqrt(sum |du|^2),
+ * max |drho|, sqrt(sum drho^2)} over all sites and components.
+ * on_device: as for lbm_init.  Synchronises. */
+lbm_status lbm_residual(lbm_t h, const double* rho_ref, const double* u_ref, int32_t on_device,
+                        double out[4]);
+
+/* Checkpoint: bytes needed by lbm_get_state (a header plus the raw stored
+ * populations). */
+lbm_status lbm_checkpoint_bytes(lbm_t h, size_t* bytes);
+
+/* Copy the state (lattice, dtype, K, dims, t, and the stored deviations
+ * g_i = f_i - w_i) to host memory `buf` of at least lbm_checkpoint_bytes(). */
+lbm_status lbm_get_state(lbm_t h, void* buf, size_t bytes);
+
+/* Restore a state written by lbm_get_state on a handle of the same lattice,
+ * dtype, K and geometry.  The next steps reproduce the original run bit for
+ * bit. */
+lbm_status lbm_set_state(lbm_t h, const void* buf, size_t bytes);
+
+/* Describe the handle. */
+lbm_status lbm_get_info(lbm_t h, lbm_info* info);
+
+/* Wait for all work issued on the handle's stream. */
+lbm_status lbm_sync(lbm_t h);
+
+/* Free the handle and every library-owned allocation; caller-bound buffers are
+ * left alone.  NULL is accepted. */
+lbm_status lbm_destroy(lbm_t h);
+
+/* Thread-local message for the last failed call on this thread ("" if none). */
+const char* lbm_last_error(void);
+
+/* The library's copy of a lattice: D, Q, T0, 2N, c (Q*3 int32, z = 0 in 2-D)
+ * and w (Q doubles).  Any output pointer may be NULL.  Host only. */
+lbm_status lbm_lattice_table(int32_t lattice, int32_t* D, int32_t* Q, double* T0, int32_t* two_n,
+                             int32_t* c, double* w);
+
+/* Measurement aid: stream `bytes` (a multiple of 16) from device buffer src to
+ * device buffer dst `reps` times with a plain vectorised copy kernel on
+ * `hip_stream`, and return the mean milliseconds per copy from HIP events.
+ * Used to calibrate traffic counters and the attainable HBM bandwidth. */
+lbm_status lbm_copy_probe(void* dst, const void* src, size_t bytes, int32_t reps, void* hip_stream,
+                          double* ms_per_copy);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

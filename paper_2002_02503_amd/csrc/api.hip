@@ -1,0 +1,759 @@
+// C-ABI implementation of liblbm.so (declared in include/lbm.h).
+//
+// Host-side responsibilities: argument validation before any device work,
+// ownership of device allocations, the two-buffer (read A / write B) step
+// sequence, capture of step sequences into HIP graphs, reduction tables,
+// checkpoint format and error reporting.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "lbm.h"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+lbm_status fail(lbm_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+lbm_status fail_hip(hipError_t e, const char* what)
+{
+    if (e == hipErrorOutOfMemory) return fail(LBM_ENOMEM, "%s: %s", what, hipGetErrorString(e));
+    return fail(LBM_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(call, what)                              \
+    do {                                                 \
+        hipError_t e_ = (call);                          \
+        if (e_ != hipSuccess) return fail_hip(e_, what); \
+    } while (0)
+
+constexpr int kChunkSites = 4096;   // sites per reduction chunk
+constexpr int kDefaultGraphChunk = 32;
+constexpr uint64_t kCkptMagic = 0x314b4350434d424cULL;  // "LBMCPCK1"
+
+struct CkptHeader {
+    uint64_t magic;
+    int32_t lattice, dtype, K, nbox;
+    int64_t nsites, t;
+    uint64_t geometry_hash;
+    uint64_t payload_bytes;
+    uint64_t reserved;  // keeps the header 64 bytes, so the payload is 64-byte aligned
+};
+static_assert(sizeof(CkptHeader) == 64, "checkpoint header layout");
+
+}  // namespace
+
+struct lbm_ctx {
+    int lattice = 0, dtype = 0, K = 0;
+    LatticeInfo lat;
+    int nbox = 0;
+    std::vector<int64_t> dims;      // nbox * 3
+    std::vector<double> tau;        // nbox
+    std::vector<int64_t> offset;    // nbox
+    int64_t nsites = 0;
+    int64_t plane = 0;              // elements per population plane
+    size_t elem = 0;                // bytes per stored population
+    size_t state_bytes = 0;
+    void* buf[2] = {nullptr, nullptr};
+    bool owns_buf = false;
+    bool bound = false;
+    int cur = 0;
+    int64_t t = 0;
+    bool initialized = false;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    int device = 0;
+    int block = 0;                  // 0 = automatic
+    int grid = 0;                   // batched: 0 = one block per tile
+    int graph_chunk = kDefaultGraphChunk;
+    // batched step tables
+    TileDesc* d_tiles = nullptr;
+    int ntiles = 0;
+    int tiles_block = 0;
+    BoxDesc* d_boxes = nullptr;
+    // reductions
+    ChunkDesc* d_chunks = nullptr;
+    int nchunks = 0;
+    int* d_box_chunk_begin = nullptr;
+    double* d_partial = nullptr;
+    double* d_out = nullptr;
+    // captured step graphs, one per starting buffer
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    int gexec_steps[2] = {0, 0};
+};
+
+namespace {
+
+bool is_single(const lbm_ctx* h) { return h->nbox == 1; }
+
+int effective_block(const lbm_ctx* h)
+{
+    if (h->block > 0) return h->block;
+    if (!is_single(h)) return 256;
+    const int64_t nx = h->dims[0];
+    int64_t b = ((nx + 63) / 64) * 64;
+    if (b > 256) b = 256;
+    return int(b);
+}
+
+uint64_t geometry_hash(const lbm_ctx* h)
+{
+    uint64_t x = 1469598103934665603ULL;  // FNV-1a over the dims
+    for (int64_t d : h->dims) {
+        for (int k = 0; k < 8; ++k) {
+            x ^= uint64_t((d >> (8 * k)) & 0xff);
+            x *= 1099511628211ULL;
+        }
+    }
+    return x;
+}
+
+lbm_status check_handle(lbm_t h)
+{
+    if (!h) return fail(LBM_EINVAL, "null handle");
+    return LBM_OK;
+}
+
+void drop_graphs(lbm_ctx* h)
+{
+    for (int p = 0; p < 2; ++p) {
+        if (h->gexec[p]) (void)hipGraphExecDestroy(h->gexec[p]);
+        h->gexec[p] = nullptr;
+        h->gexec_steps[p] = 0;
+    }
+}
+
+void free_all(lbm_ctx* h)
+{
+    drop_graphs(h);
+    if (h->owns_buf) {
+        (void)hipFree(h->buf[0]);
+        (void)hipFree(h->buf[1]);
+    }
+    h->buf[0] = h->buf[1] = nullptr;
+    (void)hipFree(h->d_tiles);
+    (void)hipFree(h->d_boxes);
+    (void)hipFree(h->d_chunks);
+    (void)hipFree(h->d_box_chunk_begin);
+    (void)hipFree(h->d_partial);
+    (void)hipFree(h->d_out);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    h->cap_stream = nullptr;
+}
+
+lbm_status validate_box(int lattice, const int64_t* d, double tau, const LatticeInfo& L, int index)
+{
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] < 1 || d[a] > INT32_MAX)
+            return fail(LBM_EINVAL, "box %d: dims[%d] = %lld outside [1, 2^31)", index, a, (long long)d[a]);
+    }
+    if (d[0] * d[1] > INT32_MAX || d[0] * d[1] * d[2] > INT32_MAX)
+        return fail(LBM_EINVAL, "box %d: site count must be below 2^31", index);
+    if (L.D == 2 && d[2] != 1) return fail(LBM_EINVAL, "box %d: a 2-D lattice needs nz == 1", index);
+    if (!std::isfinite(tau) || !(tau > 0.5)) return fail(LBM_EINVAL, "box %d: tau must be finite and > 1/2", index);
+    (void)lattice;
+    return LBM_OK;
+}
+
+lbm_status device_check(int* dev)
+{
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n < 1) return fail(LBM_ENODEV, "no usable GPU (%s)", hipGetErrorString(e));
+    HIP_TRY(hipGetDevice(dev), "hipGetDevice");
+    return LBM_OK;
+}
+
+lbm_status build_tiles(lbm_ctx* h, int block)
+{
+    if (is_single(h)) return LBM_OK;
+    if (h->d_tiles && h->tiles_block == block) return LBM_OK;
+    std::vector<TileDesc> tiles;
+    for (int b = 0; b < h->nbox; ++b) {
+        const int64_t n = h->dims[3 * b] * h->dims[3 * b + 1] * h->dims[3 * b + 2];
+        for (int64_t s = 0; s < n; s += block) tiles.push_back({b, int(s)});
+    }
+    (void)hipFree(h->d_tiles);
+    h->d_tiles = nullptr;
+    HIP_TRY(hipMalloc(&h->d_tiles, tiles.size() * sizeof(TileDesc)), "hipMalloc(tiles)");
+    HIP_TRY(hipMemcpy(h->d_tiles, tiles.data(), tiles.size() * sizeof(TileDesc), hipMemcpyHostToDevice),
+            "copy tiles");
+    h->ntiles = int(tiles.size());
+    h->tiles_block = block;
+    drop_graphs(h);
+    return LBM_OK;
+}
+
+lbm_status create_common(lbm_t* out, int32_t lattice, int32_t nbox, const int64_t* dims, const double* tau,
+                         int32_t dtype)
+{
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    LatticeInfo L;
+    if (!lattice_info(lattice, &L)) return fail(LBM_EINVAL, "unknown lattice %d", lattice);
+    if (storage_bytes(dtype) == 0) return fail(LBM_EINVAL, "unknown dtype %d", dtype);
+    if (nbox < 1) return fail(LBM_EINVAL, "nbox must be >= 1");
+    if (!dims || !tau) return fail(LBM_EINVAL, "dims or tau is NULL");
+    int64_t total = 0;
+    for (int b = 0; b < nbox; ++b) {
+        lbm_status st = validate_box(lattice, dims + 3 * b, tau[b], L, b);
+        if (st != LBM_OK) return st;
+        total += dims[3 * b] * dims[3 * b + 1] * dims[3 * b + 2];
+        if (total > INT32_MAX) return fail(LBM_EINVAL, "total site count must be below 2^31");
+    }
+    int dev = 0;
+    lbm_status st = device_check(&dev);
+    if (st != LBM_OK) return st;
+
+    lbm_ctx* h = new lbm_ctx();
+    h->lattice = lattice;
+    h->dtype = dtype;
+    h->lat = L;
+    h->K = L.k_default;
+    h->nbox = nbox;
+    h->dims.assign(dims, dims + 3 * nbox);
+    h->tau.assign(tau, tau + nbox);
+    h->offset.resize(nbox);
+    h->device = dev;
+    int64_t off = 0;
+    for (int b = 0; b < nbox; ++b) {
+        h->offset[b] = off;
+        off += dims[3 * b] * dims[3 * b + 1] * dims[3 * b + 2];
+    }
+    h->nsites = off;
+    h->elem = storage_bytes(dtype);
+    const int64_t align = int64_t(256 / h->elem);
+    h->plane = ((h->nsites + align - 1) / align) * align;
+    h->state_bytes = size_t(h->plane) * size_t(L.Q) * h->elem;
+
+    auto cleanup = [&](lbm_status s) {
+        free_all(h);
+        delete h;
+        return s;
+    };
+    hipError_t e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return cleanup(fail_hip(e, "hipStreamCreate"));
+
+    // reduction chunks (never straddle two boxes)
+    std::vector<ChunkDesc> chunks;
+    std::vector<int> begin;
+    for (int b = 0; b < nbox; ++b) {
+        begin.push_back(int(chunks.size()));
+        const int64_t n = dims[3 * b] * dims[3 * b + 1] * dims[3 * b + 2];
+        for (int64_t s = 0; s < n; s += kChunkSites) {
+            const int64_t cnt = (n - s < kChunkSites) ? (n - s) : kChunkSites;
+            chunks.push_back({h->offset[b] + s, int(cnt), b});
+        }
+    }
+    begin.push_back(int(chunks.size()));
+    h->nchunks = int(chunks.size());
+    if ((e = hipMalloc(&h->d_chunks, chunks.size() * sizeof(ChunkDesc))) != hipSuccess ||
+        (e = hipMalloc(&h->d_box_chunk_begin, begin.size() * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc(&h->d_partial, chunks.size() * 4 * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&h->d_out, size_t(nbox) * 4 * sizeof(double))) != hipSuccess)
+        return cleanup(fail_hip(e, "hipMalloc(reduction tables)"));
+    if ((e = hipMemcpy(h->d_chunks, chunks.data(), chunks.size() * sizeof(ChunkDesc), hipMemcpyHostToDevice)) !=
+            hipSuccess ||
+        (e = hipMemcpy(h->d_box_chunk_begin, begin.data(), begin.size() * sizeof(int), hipMemcpyHostToDevice)) !=
+            hipSuccess)
+        return cleanup(fail_hip(e, "copy reduction tables"));
+
+    if (nbox > 1) {
+        std::vector<BoxDesc> boxes(nbox);
+        for (int b = 0; b < nbox; ++b) {
+            boxes[b].nx = int(dims[3 * b]);
+            boxes[b].ny = int(dims[3 * b + 1]);
+            boxes[b].nz = int(dims[3 * b + 2]);
+            boxes[b].pad = 0;
+            boxes[b].offset = h->offset[b];
+            boxes[b].omega = 1.0 - 1.0 / tau[b];
+        }
+        if ((e = hipMalloc(&h->d_boxes, boxes.size() * sizeof(BoxDesc))) != hipSuccess)
+            return cleanup(fail_hip(e, "hipMalloc(boxes)"));
+        if ((e = hipMemcpy(h->d_boxes, boxes.data(), boxes.size() * sizeof(BoxDesc), hipMemcpyHostToDevice)) !=
+            hipSuccess)
+            return cleanup(fail_hip(e, "copy boxes"));
+    }
+    *out = h;
+    return LBM_OK;
+}
+
+lbm_status ensure_buffers(lbm_ctx* h)
+{
+    if (h->buf[0] && h->buf[1]) return LBM_OK;
+    void* a = nullptr;
+    void* b = nullptr;
+    hipError_t e = hipMalloc(&a, h->state_bytes);
+    if (e != hipSuccess) return fail_hip(e, "hipMalloc(population buffer)");
+    e = hipMalloc(&b, h->state_bytes);
+    if (e != hipSuccess) {
+        (void)hipFree(a);
+        return fail_hip(e, "hipMalloc(population buffer)");
+    }
+    h->buf[0] = a;
+    h->buf[1] = b;
+    h->owns_buf = true;
+    return LBM_OK;
+}
+
+// One step from buf[src_idx] into buf[src_idx ^ 1] on stream s.
+hipError_t launch_one(lbm_ctx* h, int src_idx, hipStream_t s)
+{
+    const void* src = h->buf[src_idx];
+    void* dst = h->buf[src_idx ^ 1];
+    const int block = effective_block(h);
+    if (is_single(h)) {
+        StepGeom geo;
+        geo.nx = int(h->dims[0]);
+        geo.ny = int(h->dims[1]);
+        geo.nz = int(h->dims[2]);
+        geo.xblocks = (geo.nx + block - 1) / block;
+        geo.plane = h->plane;
+        return launch_step(h->lattice, h->dtype, h->K, src, dst, geo, 1.0 - 1.0 / h->tau[0], block, s);
+    }
+    return launch_step_batch(h->lattice, h->dtype, h->K, src, dst, h->d_tiles, h->ntiles, h->d_boxes, h->plane,
+                             block, h->grid, s);
+}
+
+lbm_status build_graph(lbm_ctx* h, int parity)
+{
+    const int n = h->graph_chunk;
+    if (h->gexec[parity] && h->gexec_steps[parity] == n) return LBM_OK;
+    if (h->gexec[parity]) {
+        (void)hipGraphExecDestroy(h->gexec[parity]);
+        h->gexec[parity] = nullptr;
+    }
+    lbm_status st = build_tiles(h, effective_block(h));
+    if (st != LBM_OK) return st;
+    HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    hipError_t le = hipSuccess;
+    for (int k = 0; k < n && le == hipSuccess; ++k) le = launch_one(h, parity ^ (k & 1), h->cap_stream);
+    hipGraph_t graph = nullptr;
+    hipError_t ee = hipStreamEndCapture(h->cap_stream, &graph);
+    if (le != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail_hip(le, "kernel launch during graph capture");
+    }
+    if (ee != hipSuccess) return fail_hip(ee, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) return fail_hip(ie, "hipGraphInstantiate");
+    h->gexec[parity] = exec;
+    h->gexec_steps[parity] = n;
+    return LBM_OK;
+}
+
+lbm_status stage_in(const double* src, size_t count, int on_device, hipStream_t s, double** out, bool* temp)
+{
+    if (on_device) {
+        *out = const_cast<double*>(src);
+        *temp = false;
+        return LBM_OK;
+    }
+    double* d = nullptr;
+    HIP_TRY(hipMalloc(&d, count * sizeof(double)), "hipMalloc(staging)");
+    hipError_t e = hipMemcpyAsync(d, src, count * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return fail_hip(e, "copy to device");
+    }
+    *out = d;
+    *temp = true;
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_create(lbm_t* out, int32_t lattice, const int64_t dims[3], double tau, int32_t dtype)
+{
+    return create_common(out, lattice, 1, dims, &tau, dtype);
+}
+
+lbm_status lbm_create_batch(lbm_t* out, int32_t lattice, int32_t nbox, const int64_t* dims, const double* tau,
+                            int32_t dtype)
+{
+    return create_common(out, lattice, nbox, dims, tau, dtype);
+}
+
+lbm_status lbm_set_hermite_order(lbm_t h, int32_t K)
+{
+    if (lbm_status st = check_handle(h)) return st;
+    if (K < 2 || K > h->lat.k_max)
+        return fail(LBM_EINVAL, "Hermite order K = %d outside [2, 2N-1 = %d]", K, h->lat.k_max);
+    if (h->initialized) return fail(LBM_ESTATE, "set the Hermite order before lbm_init");
+    h->K = K;
+    drop_graphs(h);
+    return LBM_OK;
+}
+
+lbm_status lbm_set_stream(lbm_t h, void* hip_stream)
+{
+    if (lbm_status st = check_handle(h)) return st;
+    h->stream = static_cast<hipStream_t>(hip_stream);
+    return LBM_OK;
+}
+
+lbm_status lbm_state_bytes(lbm_t h, size_t* bytes_each)
+{
+    if (lbm_status st = check_handle(h)) return st;
+    if (!bytes_each) return fail(LBM_EINVAL, "bytes_each is NULL");
+    *bytes_each = h->state_bytes;
+    return LBM_OK;
+}
+
+lbm_status lbm_bind_state(lbm_t h, void* buf_a, void* buf_b, size_t bytes_each)
+{
+    if (lbm_status st = check_handle(h)) return st;
+    if (!buf_a || !buf_b || buf_a == buf_b) return fail(LBM_EINVAL, "need two distinct non-NULL buffers");
+    if (bytes_each < h->state_bytes)
+        return fail(LBM_EINVAL, "buffers hold %zu bytes, need %zu", bytes_each, h->state_bytes);
+    if ((reinterpret_cast<uintptr_t>(buf_a) | reinterpret_cast<uintptr_t>(buf_b)) & 255u)
+        return fail(LBM_EINVAL, "buffers must be 256-byte aligned");
+    if (h->initialized || h->buf[0]) return fail(LBM_ESTATE, "bind buffers before lbm_init / lbm_set_state");
+    h->buf[0] = buf_a;
+    h->buf[1] = buf_b;
+    h->owns_buf = false;
+    h->bound = true;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_graph_chunk(lbm_t h, int32_t steps)
+{
+    if (lbm_status st = check_handle(h)) return st;
+    if (steps < 1 || steps > 4096) return fail(LBM_EINVAL, "graph chunk must be in [1, 4096]");
+    h->graph_chunk = steps;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_launch(lbm_t h, int32_t block, int32_t grid)
+{
+    if (lbm_status st = check_handle(h)) return st;
+    if (!(block == 0 || block == 64 || block == 128 || block == 256))
+        return fail(LBM_EINVAL, "block must be 0, 64, 128 or 256");
+    if (grid < 0) return fail(LBM_EINVAL, "grid must be >= 0");
+    if (h->initialized) return fail(LBM_ESTATE, "set the launch shape before lbm_init");
+    h->block = block;
+    h->grid = grid;
+    drop_graphs(h);
+    return LBM_OK;
+}
+
+lbm_status lbm_init(lbm_t h, const double* rho, const double* u, int32_t on_device)
+{
+    if (lbm_status st = check_handle(h)) return st;
+    if (!rho || !u) return fail(LBM_EINVAL, "rho or u is NULL");
+    HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+    if (lbm_status st = ensure_buffers(h)) return st;
+    if (lbm_status st = build_tiles(h, effective_block(h))) return st;
+    const size_t n = size_t(h->nsites);
+    double *drho = nullptr, *du = nullptr;
+    bool t1 = false, t2 = false;
+    if (lbm_status st = stage_in(rho, n, on_device, h->stream, &drho, &t1)) return st;
+    if (lbm_status st = stage_in(u, n * h->lat.D, on_device, h->stream, &du, &t2)) {
+        if (t1) (void)hipFree(drho);
+        return st;
+    }
+    hipError_t e = launch_init(h->lattice, h->dtype, h->K, drho, du, h->buf[0], h->nsites, h->plane, h->stream);
+    hipError_t e2 = hipStreamSynchronize(h->stream);
+    if (t1) (void)hipFree(drho);
+    if (t2) (void)hipFree(du);
+    if (e != hipSuccess) return fail_hip(e, "init kernel");
+    if (e2 != hipSuccess) return fail_hip(e2, "init synchronize");
+    h->cur = 0;
+    h->t = 0;
+    h->initialized = true;
+    return LBM_OK;
+}
+
+lbm_status lbm_prepare(lbm_t h)
+{
+    if (lbm_status st = check_handle(h)) return st;
+    if (!h->initialized) return fail(LBM_ESTATE, "lbm_prepare before lbm_init");
+    HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+    for (int p = 0; p < 2; ++p)
+        if (lbm_status st = build_graph(h, p)) return st;
+    return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_t h, int64_t n)
+{
+    if (lbm_status st = check_handle(h)) return st;
+    if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
+    if (!h->initialized) return fail(LBM_ESTATE, "lbm_step before lbm_init");
+    if (n == 0) return LBM_OK;
+    HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+    if (lbm_status st = build_tiles(h, effective_block(h))) return st;
+    const int G = h->graph_chunk;
+    int64_t left = n;
+    if (G > 1) {
+        while (left >= G) {
+            if (lbm_status st = build_graph(h, h->cur)) return st;
+            HIP_TRY(hipGraphLaunch(h->gexec[h->cur], h->stream), "hipGraphLaunch");
+            h->cur ^= (G & 1);
+            h->t += G;
+            left -= G;
+        }
+    }
+    for (; left > 0; --left) {
+        hipError_t e = launch_one(h, h->cur, h->stream);
+        if (e != hipSuccess) return fail_hip(e, "step kernel launch");
+        h->cur ^= 1;
+        h->t += 1;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_moments(lbm_t h, double* rho, double* u, int32_t on_device)
+{
+    if (lbm_status st = check_handle(h)) return st;
+    if (!rho || !u) return fail(LBM_EINVAL, "rho or u is NULL");
+    if (!h->initialized) return fail(LBM_ESTATE, "lbm_moments before lbm_init");
+    HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+    const size_t n = size_t(h->nsites);
+    const int D = h->lat.D;
+    double *drho = rho, *du = u;
+    if (!on_device) {
+        HIP_TRY(hipMalloc(&drho, n * (1 + D) * sizeof(double)), "hipMalloc(moments)");
+        du = drho + n;
+    }
+    hipError_t e = launch_moments(h->lattice, h->dtype, h->buf[h->cur], drho, du, h->nsites, h->plane, h->stream);
+    if (e == hipSuccess && !on_device) {
+        e = hipMemcpyAsync(rho, drho, n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(u, du, n * D * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    }
+    hipError_t e2 = hipStreamSynchronize(h->stream);
+    if (!on_device) (void)hipFree(drho);
+    if (e != hipSuccess) return fail_hip(e, "moments");
+    if (e2 != hipSuccess) return fail_hip(e2, "moments synchronize");
+    return LBM_OK;
+}
+
+lbm_status lbm_totals(lbm_t h, double* out)
+{
+    if (lbm_status st = check_handle(h)) return st;
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    if (!h->initialized) return fail(LBM_ESTATE, "lbm_totals before lbm_init");
+    HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+    hipError_t e = launch_totals(h->lattice, h->dtype, h->buf[h->cur], h->d_chunks, h->nchunks,
+                                 h->d_box_chunk_begin, h->nbox, h->plane, h->d_partial, h->d_out, h->stream);
+    if (e != hipSuccess) return fail_hip(e, "totals kernels");
+    HIP_TRY(hipMemcpyAsync(out, h->d_out, size_t(h->nbox) * 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream),
+            "copy totals");
+    HIP_TRY(hipStreamSynchronize(h->stream), "totals synchronize");
+    for (int b = 0; b < h->nbox; ++b) {
+        bool ok = out[4 * b] > 0.0;
+        for (int k = 0; k < 4; ++k) ok = ok && std::isfinite(out[4 * b + k]);
+        if (!ok) return fail(LBM_ENUMERIC, "box %d: non-finite totals or non-positive mass", b);
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_residual(lbm_t h, const double* rho_ref, const double* u_ref, int32_t on_device, double out[4])
+{
+    if (lbm_status st = check_handle(h)) return st;
+    if (!rho_ref || !u_ref || !out) return fail(LBM_EINVAL, "NULL argument");
+    if (!h->initialized) return fail(LBM_ESTATE, "lbm_residual before lbm_init");
+    HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+    const size_t n = size_t(h->nsites);
+    double *dr = nullptr, *du = nullptr;
+    bool t1 = false, t2 = false;
+    if (lbm_status st = stage_in(rho_ref, n, on_device, h->stream, &dr, &t1)) return st;
+    if (lbm_status st = stage_in(u_ref, n * h->lat.D, on_device, h->stream, &du, &t2)) {
+        if (t1) (void)hipFree(dr);
+        return st;
+    }
+    hipError_t e = launch_residual(h->lattice, h->dtype, h->buf[h->cur], dr, du, h->d_chunks, h->nchunks,
+                                   h->nsites, h->plane, h->d_partial, h->d_out, h->stream);
+    double tmp[4] = {0, 0, 0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(tmp, h->d_out, 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    hipError_t e2 = hipStreamSynchronize(h->stream);
+    if (t1) (void)hipFree(dr);
+    if (t2) (void)hipFree(du);
+    if (e != hipSuccess) return fail_hip(e, "residual kernels");
+    if (e2 != hipSuccess) return fail_hip(e2, "residual synchronize");
+    out[0] = tmp[0];
+    out[1] = std::sqrt(tmp[1]);
+    out[2] = tmp[2];
+    out[3] = std::sqrt(tmp[3]);
+    return LBM_OK;
+}
+
+lbm_status lbm_checkpoint_bytes(lbm_t h, size_t* bytes)
+{
+    if (lbm_status st = check_handle(h)) return st;
+    if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
+    *bytes = sizeof(CkptHeader) + size_t(h->lat.Q) * size_t(h->nsites) * h->elem;
+    return LBM_OK;
+}
+
+lbm_status lbm_get_state(lbm_t h, void* buf, size_t bytes)
+{
+    if (lbm_status st = check_handle(h)) return st;
+    size_t need = 0;
+    lbm_checkpoint_bytes(h, &need);
+    if (!buf || bytes < need) return fail(LBM_EINVAL, "checkpoint buffer needs %zu bytes", need);
+    if (!h->initialized) return fail(LBM_ESTATE, "lbm_get_state before lbm_init");
+    HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+    CkptHeader hd;
+    std::memset(&hd, 0, sizeof(hd));
+    hd.magic = kCkptMagic;
+    hd.lattice = h->lattice;
+    hd.dtype = h->dtype;
+    hd.K = h->K;
+    hd.nbox = h->nbox;
+    hd.nsites = h->nsites;
+    hd.t = h->t;
+    hd.geometry_hash = geometry_hash(h);
+    hd.payload_bytes = need - sizeof(CkptHeader);
+    std::memcpy(buf, &hd, sizeof(hd));
+    char* dst = static_cast<char*>(buf) + sizeof(hd);
+    const char* src = static_cast<const char*>(h->buf[h->cur]);
+    const size_t pb = size_t(h->nsites) * h->elem;
+    for (int i = 0; i < h->lat.Q; ++i)
+        HIP_TRY(hipMemcpyAsync(dst + i * pb, src + size_t(i) * size_t(h->plane) * h->elem, pb, hipMemcpyDeviceToHost,
+                               h->stream),
+                "copy state to host");
+    HIP_TRY(hipStreamSynchronize(h->stream), "get_state synchronize");
+    return LBM_OK;
+}
+
+lbm_status lbm_set_state(lbm_t h, const void* buf, size_t bytes)
+{
+    if (lbm_status st = check_handle(h)) return st;
+    size_t need = 0;
+    lbm_checkpoint_bytes(h, &need);
+    if (!buf || bytes < need) return fail(LBM_EINVAL, "checkpoint buffer needs %zu bytes", need);
+    CkptHeader hd;
+    std::memcpy(&hd, buf, sizeof(hd));
+    if (hd.magic != kCkptMagic) return fail(LBM_EINVAL, "not a checkpoint written by lbm_get_state");
+    if (hd.lattice != h->lattice || hd.dtype != h->dtype || hd.K != h->K || hd.nbox != h->nbox ||
+        hd.nsites != h->nsites || hd.geometry_hash != geometry_hash(h) || hd.payload_bytes != need - sizeof(hd))
+        return fail(LBM_EINVAL, "checkpoint does not match this handle (lattice, dtype, K or geometry)");
+    HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+    if (lbm_status st = ensure_buffers(h)) return st;
+    if (lbm_status st = build_tiles(h, effective_block(h))) return st;
+    const char* src = static_cast<const char*>(buf) + sizeof(hd);
+    char* dst = static_cast<char*>(h->buf[0]);
+    const size_t pb = size_t(h->nsites) * h->elem;
+    for (int i = 0; i < h->lat.Q; ++i)
+        HIP_TRY(hipMemcpyAsync(dst + size_t(i) * size_t(h->plane) * h->elem, src + i * pb, pb, hipMemcpyHostToDevice,
+                               h->stream),
+                "copy state to device");
+    HIP_TRY(hipStreamSynchronize(h->stream), "set_state synchronize");
+    h->cur = 0;
+    h->t = hd.t;
+    h->initialized = true;
+    return LBM_OK;
+}
+
+lbm_status lbm_get_info(lbm_t h, lbm_info* info)
+{
+    if (lbm_status st = check_handle(h)) return st;
+    if (!info) return fail(LBM_EINVAL, "info is NULL");
+    std::memset(info, 0, sizeof(*info));
+    info->lattice = h->lattice;
+    info->dtype = h->dtype;
+    info->D = h->lat.D;
+    info->Q = h->lat.Q;
+    info->two_n = h->lat.two_n;
+    info->K = h->K;
+    info->T0 = h->lat.T0;
+    info->nbox = h->nbox;
+    for (int a = 0; a < 3; ++a) info->dims[a] = h->dims[a];
+    info->nsites = h->nsites;
+    info->t = h->t;
+    info->bytes_per_site_update = int64_t(2 * h->lat.Q) * int64_t(h->elem);
+    info->state_bytes = h->state_bytes;
+    info->block = effective_block(h);
+    info->grid = h->grid;
+    info->graph_chunk = h->graph_chunk;
+    return LBM_OK;
+}
+
+lbm_status lbm_sync(lbm_t h)
+{
+    if (lbm_status st = check_handle(h)) return st;
+    HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    return LBM_OK;
+}
+
+lbm_status lbm_destroy(lbm_t h)
+{
+    if (!h) return LBM_OK;
+    (void)hipSetDevice(h->device);
+    (void)hipStreamSynchronize(h->stream);
+    free_all(h);
+    delete h;
+    return LBM_OK;
+}
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+
+lbm_status lbm_lattice_table(int32_t lattice, int32_t* D, int32_t* Q, double* T0, int32_t* two_n, int32_t* c,
+                             double* w)
+{
+    LatticeInfo L;
+    if (!lattice_info(lattice, &L)) return fail(LBM_EINVAL, "unknown lattice %d", lattice);
+    if (D) *D = L.D;
+    if (Q) *Q = L.Q;
+    if (T0) *T0 = L.T0;
+    if (two_n) *two_n = L.two_n;
+    for (int i = 0; i < L.Q; ++i) {
+        if (c)
+            for (int a = 0; a < 3; ++a) c[i * 3 + a] = L.c[i * 3 + a];
+        if (w) w[i] = L.w[i];
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_copy_probe(void* dst, const void* src, size_t bytes, int32_t reps, void* hip_stream,
+                          double* ms_per_copy)
+{
+    if (!dst || !src || !ms_per_copy || reps < 1 || bytes == 0 || (bytes % 16) != 0)
+        return fail(LBM_EINVAL, "copy probe needs non-NULL buffers, reps >= 1 and bytes a positive multiple of 16");
+    int dev = 0;
+    if (lbm_status st = device_check(&dev)) return st;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+    hipError_t e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail_hip(e, "hipEventCreate");
+    }
+    e = launch_copy(dst, src, bytes, s);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_copy(dst, src, bytes, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail_hip(e, "copy probe");
+    *ms_per_copy = double(ms) / reps;
+    return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,143 @@
+// Lattice descriptors for the GPU path: velocity sets c_i, weights w_i and the
+// lattice temperature T0 of D2Q9, D3Q19 and D3Q39.
+//
+// A lattice is "2N-th order isotropic" when sum_i w_i c_i...c_i (n times)
+// equals T0^(n/2) times the n-th order Kronecker-delta tensor for even
+// n <= 2N and vanishes for odd n (eq. iso, section "Basic Filtered Collision
+// Formulation").  D2Q9 and D3Q19 have 2N = 4 with T0 = 1/3; D3Q39 has 2N = 6
+// with T0 = 2/3 (its six shell weights are the unique positive solution of
+// eq. iso through sixth order).
+//
+// Weight quantum.  Every weight is an integer multiple of 1/S (S = 36 for
+// D2Q9 and D3Q19, 6480 for D3Q39), so W_i = S w_i are small integers, exact in
+// any floating-point type.  The kernels keep the populations in these units
+// (see collide.hpp): no rounded weight ever enters the arithmetic.
+//
+// Every table is a compile-time constant.  Kernels index them only with
+// compile-time indices (through `unroll`), so each c_i component and weight is
+// folded into the instruction stream: zero components disappear and +/-1
+// multiplications become adds.
+#pragma once
+
+#include <cstdint>
+#include <type_traits>
+#include <utility>
+
+#if defined(__HIP__)
+#include <hip/hip_runtime.h>
+#else
+#define __host__
+#define __device__
+#define __forceinline__ inline
+#endif
+
+namespace lbm {
+
+enum LatticeId : int { kD2Q9 = 0, kD3Q19 = 1, kD3Q39 = 2 };
+
+struct D2Q9 {
+    static constexpr int id = kD2Q9;
+    static constexpr int D = 2, Q = 9, TWO_N = 4, K_DEFAULT = 3, K_MAX = 3;
+    static constexpr int R = 1;  // largest |c_i component|
+    static constexpr double T0 = 1.0 / 3.0, INV_T0 = 3.0;
+    static constexpr int S = 36;
+    static constexpr int W[Q] = {16, 4, 4, 4, 4, 1, 1, 1, 1};
+    static constexpr int8_t c[Q][3] = {
+        {0, 0, 0},
+        {1, 0, 0}, {0, 1, 0}, {-1, 0, 0}, {0, -1, 0},
+        {1, 1, 0}, {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}};
+    static constexpr double w[Q] = {
+        4.0 / 9.0,
+        1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+        1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+};
+
+struct D3Q19 {
+    static constexpr int id = kD3Q19;
+    static constexpr int D = 3, Q = 19, TWO_N = 4, K_DEFAULT = 3, K_MAX = 3;
+    static constexpr int R = 1;
+    static constexpr double T0 = 1.0 / 3.0, INV_T0 = 3.0;
+    static constexpr int S = 36;
+    static constexpr int W[Q] = {12, 2, 2, 2, 2, 2, 2, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1};
+    static constexpr int8_t c[Q][3] = {
+        {0, 0, 0},
+        {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+        {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
+        {1, 0, 1}, {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+        {0, 1, 1}, {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+    static constexpr double w[Q] = {
+        1.0 / 3.0,
+        1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,
+        1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+        1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+        1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+};
+
+struct D3Q39 {
+    static constexpr int id = kD3Q39;
+    static constexpr int D = 3, Q = 39, TWO_N = 6, K_DEFAULT = 4, K_MAX = 5;
+    static constexpr int R = 3;
+    static constexpr double T0 = 2.0 / 3.0, INV_T0 = 1.5;
+    static constexpr int S = 6480;
+    static constexpr int W[Q] = {540, 540, 540, 540, 540, 540, 540,
+                                 240, 240, 240, 240, 240, 240, 240, 240,
+                                 96, 96, 96, 96, 96, 96,
+                                 15, 15, 15, 15, 15, 15, 15, 15, 15, 15, 15, 15,
+                                 4, 4, 4, 4, 4, 4};
+    static constexpr int8_t c[Q][3] = {
+        {0, 0, 0},
+        // |c| = 1, axis
+        {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+        // (+-1, +-1, +-1)
+        {1, 1, 1}, {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1},
+        {1, -1, 1}, {-1, 1, -1}, {-1, 1, 1}, {1, -1, -1},
+        // (+-2, 0, 0) and permutations
+        {2, 0, 0}, {-2, 0, 0}, {0, 2, 0}, {0, -2, 0}, {0, 0, 2}, {0, 0, -2},
+        // (+-2, +-2, 0) and permutations
+        {2, 2, 0}, {-2, -2, 0}, {2, -2, 0}, {-2, 2, 0},
+        {2, 0, 2}, {-2, 0, -2}, {2, 0, -2}, {-2, 0, 2},
+        {0, 2, 2}, {0, -2, -2}, {0, 2, -2}, {0, -2, 2},
+        // (+-3, 0, 0) and permutations
+        {3, 0, 0}, {-3, 0, 0}, {0, 3, 0}, {0, -3, 0}, {0, 0, 3}, {0, 0, -3}};
+    static constexpr double w[Q] = {
+        1.0 / 12.0,
+        1.0 / 12.0, 1.0 / 12.0, 1.0 / 12.0, 1.0 / 12.0, 1.0 / 12.0, 1.0 / 12.0,
+        1.0 / 27.0, 1.0 / 27.0, 1.0 / 27.0, 1.0 / 27.0,
+        1.0 / 27.0, 1.0 / 27.0, 1.0 / 27.0, 1.0 / 27.0,
+        2.0 / 135.0, 2.0 / 135.0, 2.0 / 135.0, 2.0 / 135.0, 2.0 / 135.0, 2.0 / 135.0,
+        1.0 / 432.0, 1.0 / 432.0, 1.0 / 432.0, 1.0 / 432.0,
+        1.0 / 432.0, 1.0 / 432.0, 1.0 / 432.0, 1.0 / 432.0,
+        1.0 / 432.0, 1.0 / 432.0, 1.0 / 432.0, 1.0 / 432.0,
+        1.0 / 1620.0, 1.0 / 1620.0, 1.0 / 1620.0, 1.0 / 1620.0, 1.0 / 1620.0, 1.0 / 1620.0};
+};
+
+// W_i = S w_i exactly, and the W_i add up to S.
+template <class L>
+constexpr bool integer_weights_consistent()
+{
+    int sum = 0;
+    for (int i = 0; i < L::Q; ++i) {
+        const double d = L::S * L::w[i] - L::W[i];
+        if (d > 1e-12 || d < -1e-12) return false;
+        sum += L::W[i];
+    }
+    return sum == L::S;
+}
+static_assert(integer_weights_consistent<D2Q9>(), "D2Q9 weight quantum");
+static_assert(integer_weights_consistent<D3Q19>(), "D3Q19 weight quantum");
+static_assert(integer_weights_consistent<D3Q39>(), "D3Q39 weight quantum");
+
+// Calls f(std::integral_constant<int, i>{}) for i = 0 .. N-1, fully unrolled.
+template <class F, int... I>
+__host__ __device__ __forceinline__ void unroll_impl(F&& f, std::integer_sequence<int, I...>)
+{
+    (f(std::integral_constant<int, I>{}), ...);
+}
+
+template <int N, class F>
+__host__ __device__ __forceinline__ void unroll(F&& f)
+{
+    unroll_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+}  // namespace lbm

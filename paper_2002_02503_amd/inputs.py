@@ -10,6 +10,8 @@ coordinates are the integer site indices.
 """
 from __future__ import annotations
 
+import os
+
 import numpy as np
 
 # Seeds of the two randomised workloads.
@@ -56,29 +58,39 @@ def shear_wave(dims, amplitude: float, U=(0.0, 0.0, 0.0), D: int = 3):
 def turbulence(n: int, k0: float = 4.0, u_rms: float = 0.04, seed: int = TURBULENCE_SEED):
     """Random-phase solenoidal velocity field on an n^3 periodic box.
 
-    Each Fourier component at integer wavevector k (|k| > 0) gets amplitude
-    |k| exp(-|k|^2 / k0^2) with an independent uniform phase per velocity
-    component, so that the shell energy spectrum is proportional to
-    k^4 exp(-2 k^2 / k0^2).  The field is projected onto k . u_hat = 0, the real
-    part of its inverse FFT is taken, and it is scaled so that the per-component
-    rms velocity sqrt(<|u|^2> / 3) equals u_rms.  rho = 1."""
+    Fourier components live on integer wavevectors k with every |k_a| <= kc,
+    kc = min(n // 2 - 1, 8 k0) (beyond 8 k0 the amplitude is below 1e-26 of its
+    peak).  Each component gets amplitude |k| exp(-|k|^2 / k0^2) and an
+    independent uniform phase per velocity component, drawn in C order over
+    (component, kz, ky, kx) from numpy's default generator with `seed`, so the
+    shell energy spectrum is proportional to k^4 exp(-2 k^2 / k0^2).  The field
+    is projected onto k . u_hat = 0, the real part of its inverse FFT is taken,
+    and it is scaled so that the per-component rms velocity sqrt(<|u|^2> / 3)
+    equals u_rms.  rho = 1."""
+    import scipy.fft as sfft
+
     rng = np.random.default_rng(seed)
-    kk = np.fft.fftfreq(n, d=1.0 / n)  # integer wavenumbers
+    kc = int(min(n // 2 - 1, 8 * k0))
+    m = 2 * kc + 1
+    kk = np.arange(-kc, kc + 1, dtype=np.float64)
     kz, ky, kx = np.meshgrid(kk, kk, kk, indexing="ij")
     k2 = kx * kx + ky * ky + kz * kz
     amp = np.sqrt(k2) * np.exp(-k2 / (k0 * k0))
-    amp[0, 0, 0] = 0.0
-    kvec = (kx, ky, kz)
-    uh = []
-    for a in range(3):
-        phase = rng.uniform(0.0, 2.0 * np.pi, size=(n, n, n))
-        uh.append(amp * np.exp(1j * phase))
+    phase = rng.uniform(0.0, 2.0 * np.pi, size=(3, m, m, m))
+    uh = amp * np.exp(1j * phase)
     k2s = np.where(k2 == 0, 1.0, k2)
     kdotu = kx * uh[0] + ky * uh[1] + kz * uh[2]
+    uh[0] -= kx * kdotu / k2s
+    uh[1] -= ky * kdotu / k2s
+    uh[2] -= kz * kdotu / k2s
+    idx = np.arange(-kc, kc + 1) % n  # FFT storage positions of the kept modes
     u = np.zeros((3, n, n, n))
+    workers = os.cpu_count() or 1
+    full = np.zeros((n, n, n), dtype=np.complex128)
     for a in range(3):
-        uh_a = uh[a] - kvec[a] * kdotu / k2s
-        u[a] = np.real(np.fft.ifftn(uh_a))
+        full[...] = 0.0
+        full[np.ix_(idx, idx, idx)] = uh[a]
+        u[a] = np.real(sfft.ifftn(full, workers=workers))
     scale = u_rms / np.sqrt(np.mean(np.sum(u * u, axis=0)) / 3.0)
     u *= scale
     return np.ones((n, n, n)), u

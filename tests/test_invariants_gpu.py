@@ -1,0 +1,196 @@
+"""GPU invariants of the library that need no oracle: collision fixed points,
+conservation, poisoned destination buffers, checkpoint/resume, graph versus
+direct launches, streams, device-pointer I/O, the FP64 reductions and the
+error paths of the ABI."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import rel_u, run_gpu, run_oracle
+from paper_2002_02503_amd import lbm
+
+pytestmark = pytest.mark.gpu
+
+
+def _fields(dims, seed=0, amp=0.05):
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = dims
+    u = rng.uniform(-amp, amp, size=(3, nz, ny, nx))
+    rho = 1.0 + rng.uniform(-0.01, 0.01, size=(nz, ny, nx))
+    return rho, u
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+@pytest.mark.parametrize("lattice", ["D3Q19", "D3Q39"])
+def test_uniform_flow_stays_uniform(lattice, dtype):
+    dims = (64, 4, 3)
+    U = np.array([0.08, -0.05, 0.03])
+    rho = np.full((3, 4, 64), 1.02)
+    u = np.broadcast_to(U.reshape(3, 1, 1, 1), (3, 3, 4, 64)).copy()
+    r, uu = run_gpu(lattice, dims, 0.6, dtype, rho, u, 50)
+    tol = 1e-14 if dtype == "fp64" else 1e-7
+    assert np.abs(uu - u).max() < tol
+    assert np.abs(r - rho).max() < tol
+    # every site identical, bit for bit
+    assert np.all(uu == uu[:, :1, :1, :1])
+
+
+def test_poisoned_buffers_are_fully_overwritten():
+    """Both population buffers filled with NaN bytes before init: every site
+    of every step's destination is written, so nothing non-finite appears,
+    and the result equals a run on clean buffers bit for bit."""
+    dims = (100, 7, 6)
+    rho, u = _fields(dims, 1)
+    clean = run_gpu("D3Q19", dims, 0.6, "fp32", rho, u, 7)
+    with lbm.Simulation("D3Q19", dims, 0.6, dtype="fp32") as sim:
+        for b in sim._bufs:
+            b.fill_(0xFF)
+        sim.init(rho, u).step(7)
+        r, uu = sim.moments()
+    assert np.isfinite(r).all() and np.isfinite(uu).all()
+    assert np.array_equal(r, clean[0]) and np.array_equal(uu, clean[1])
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "fp16", "bf16", "fp64"])
+def test_checkpoint_resume_is_bitwise(dtype):
+    dims = (48, 10, 9)
+    rho, u = _fields(dims, 2)
+    with lbm.Simulation("D3Q19", dims, 0.58, dtype=dtype) as a:
+        a.init(rho, u).step(13)
+        ck = a.get_state()
+        a.step(17)
+        ra, ua = a.moments()
+        assert a.t == 30
+    with lbm.Simulation("D3Q19", dims, 0.58, dtype=dtype) as b:
+        b.set_state(ck)
+        assert b.t == 13
+        b.step(17)
+        rb, ub = b.moments()
+    assert np.array_equal(ra, rb) and np.array_equal(ua, ub)
+
+
+def test_checkpoint_rejects_other_geometry():
+    rho, u = _fields((16, 8, 8), 3)
+    with lbm.Simulation("D3Q19", (16, 8, 8), 0.6) as a:
+        ck = a.init(rho, u).get_state()
+    with lbm.Simulation("D3Q19", (8, 16, 8), 0.6) as b:
+        with pytest.raises(lbm.LBMError) as e:
+            b.set_state(ck)
+        assert e.value.name == "LBM_EINVAL"
+
+
+@pytest.mark.parametrize("chunk", [1, 2, 7, 16])
+def test_graph_launches_equal_direct_launches(chunk):
+    """Steps issued as captured graphs (chunks of `chunk` steps plus a
+    remainder) compute the same bits as one launch per step; repeated graph
+    replays with host work between them stay identical."""
+    dims = (80, 9, 7)
+    rho, u = _fields(dims, 4)
+    ref = run_gpu("D3Q19", dims, 0.6, "fp32", rho, u, 40, graph_chunk=1)
+    with lbm.Simulation("D3Q19", dims, 0.6, dtype="fp32", graph_chunk=chunk) as sim:
+        sim.init(rho, u).prepare()
+        for n in [5, 20, 15]:
+            sim.step(n)
+            sim.sync()
+            _ = np.sum(np.arange(1000))  # host work between replays
+        r, uu = sim.moments()
+    assert np.array_equal(r, ref[0]) and np.array_equal(uu, ref[1])
+
+
+def test_runs_on_a_caller_stream():
+    dims = (64, 8, 8)
+    rho, u = _fields(dims, 5)
+    ref = run_gpu("D3Q19", dims, 0.6, "fp32", rho, u, 20)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with lbm.Simulation("D3Q19", dims, 0.6, dtype="fp32", stream=s) as sim:
+            sim.init(rho, u).step(20)
+            r, uu = sim.moments()
+    assert np.array_equal(r, ref[0]) and np.array_equal(uu, ref[1])
+
+
+def test_device_pointer_io_matches_host_io():
+    dims = (40, 6, 5)
+    rho, u = _fields(dims, 6)
+    ref = run_gpu("D3Q19", dims, 0.6, "fp32", rho, u, 9)
+    with lbm.Simulation("D3Q19", dims, 0.6, dtype="fp32") as sim:
+        sim.init(torch.from_numpy(rho).cuda(), torch.from_numpy(u).cuda()).step(9)
+        r, uu = sim.moments(device=True)
+    assert np.array_equal(r.cpu().numpy(), ref[0]) and np.array_equal(uu.cpu().numpy(), ref[1])
+
+
+def test_totals_and_residual_match_numpy():
+    dims = (50, 11, 7)
+    rho, u = _fields(dims, 7)
+    r_ref, u_ref = run_oracle("D3Q19", dims, 0.6, rho, u, 12)
+    with lbm.Simulation("D3Q19", dims, 0.6, dtype="fp64") as sim:
+        sim.init(rho, u)
+        t0 = sim.totals()[0]
+        sim.step(12)
+        t1 = sim.totals()[0]
+        r, uu = sim.moments()
+        res = sim.residual(r_ref, u_ref)
+    assert abs(t1[0] - np.sum(r)) < 1e-10
+    assert np.abs(t1[1:] - np.sum(r * uu, axis=(1, 2, 3))).max() < 1e-12
+    assert abs(t1[0] - t0[0]) / t0[0] < 1e-14
+    assert np.abs(t1[1:] - t0[1:]).max() / t0[0] < 1e-14
+    du = uu - u_ref
+    assert abs(res["u_max"] - np.abs(du).max()) <= 1e-18 + 1e-12 * np.abs(du).max()
+    assert abs(res["u_l2"] - np.sqrt(np.sum(du * du))) <= 1e-12 * np.sqrt(np.sum(du * du)) + 1e-18
+    dr = r - r_ref
+    assert abs(res["rho_max"] - np.abs(dr).max()) <= 1e-18 + 1e-12 * np.abs(dr).max()
+
+
+def test_error_paths():
+    dims = (16, 8, 8)
+    rho, u = _fields(dims, 8)
+    with lbm.Simulation("D3Q19", dims, 0.6) as sim:
+        with pytest.raises(lbm.LBMError) as e:
+            sim.step(1)
+        assert e.value.name == "LBM_ESTATE"
+        with pytest.raises(lbm.LBMError) as e:
+            sim.moments()
+        assert e.value.name == "LBM_ESTATE"
+        for K in [1, 4]:
+            with pytest.raises(lbm.LBMError) as e:
+                lbm._check(sim.lib.lbm_set_hermite_order(sim.h, K))
+            assert e.value.name == "LBM_EINVAL"
+        sim.init(rho, u)
+        with pytest.raises(lbm.LBMError) as e:
+            lbm._check(sim.lib.lbm_set_hermite_order(sim.h, 2))
+        assert e.value.name == "LBM_ESTATE"
+        with pytest.raises(lbm.LBMError) as e:
+            sim.step(-1)
+        assert e.value.name == "LBM_EINVAL"
+        with pytest.raises(lbm.LBMError) as e:
+            lbm._check(sim.lib.lbm_set_launch(sim.h, 96, 0))
+        assert e.value.name == "LBM_EINVAL"
+
+
+def test_non_finite_state_is_reported():
+    """A checkpoint whose populations are NaN restores fine, and lbm_totals
+    then reports LBM_ENUMERIC (the check is on the host, the kernels simply
+    propagate the NaN)."""
+    dims = (16, 8, 8)
+    rho, u = _fields(dims, 9)
+    with lbm.Simulation("D3Q19", dims, 0.6, dtype="fp32") as sim:
+        ck = sim.init(rho, u).get_state()
+        payload = ck[64:].view(np.float32)
+        payload[:] = np.nan
+        sim.set_state(ck)
+        with pytest.raises(lbm.LBMError) as e:
+            sim.totals()
+        assert e.value.name == "LBM_ENUMERIC"
+
+
+def test_batch_of_equal_boxes_equals_single_boxes():
+    """Two identical boxes in one batch each evolve exactly like the single box."""
+    dims = (24, 20, 18)
+    rho, u = _fields(dims, 10)
+    single = run_gpu("D3Q19", dims, 0.65, "fp32", rho, u, 30)
+    with lbm.Simulation("D3Q19", [dims, dims], [0.65, 0.65], dtype="fp32") as sim:
+        sim.init(np.concatenate([rho.ravel()] * 2), np.concatenate([u.reshape(3, -1)] * 2, axis=1))
+        sim.step(30)
+        r, uu = sim.moments()
+    for k, ub in enumerate(sim.split_boxes(uu)):
+        assert np.abs(ub - single[1]).max() < 1e-7, k
