@@ -178,7 +178,8 @@ def test_batched_256_boxes_fp32():
     dm = np.abs(tot1[:, 0] - mass) / mass
     dp = np.abs(tot1[:, 1:] - tot0[:, 1:]).max(axis=1) / mass
     print(f"batched: worst mass drift {dm.max():.2e}, momentum drift {dp.max():.2e}", flush=True)
-    assert np.all(dm < 5e-8) and np.all(dp < 5e-8)
+    # single-precision round-off over 1000 steps (FP32 epsilon 6e-8)
+    assert np.all(dm < 2e-7) and np.all(dp < 2e-7)
     worst = 0.0
     for k in range(0, len(boxes), 16):
         nx, ny, nz = boxes[k]["dims"]
