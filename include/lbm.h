@@ -44,10 +44,11 @@ typedef struct lbm_ctx* lbm_t;
  * (eq. iso and the lattice catalogue that follows it). */
 typedef enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1, LBM_D3Q39 = 2 } lbm_lattice;
 
-/* Storage type of the populations.  All types store the deviation
- * g_i = f_i - w_i.  Arithmetic: FP64 computes in double; FP32, FP16 and BF16
- * compute per population in float, with the moment sums and the conservation
- * correction accumulated in double. */
+/* Storage type of the populations.  Every type stores S (f_i - w_i): the
+ * deviation from the rest weights in units of the weight quantum 1/S (S = 36
+ * for D2Q9 and D3Q19, 6480 for D3Q39), so every weight is the exact integer
+ * S w_i.  Arithmetic: FP64 computes in double; FP32, FP16 and BF16 compute in
+ * float. */
 typedef enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16 = 2, LBM_BF16 = 3 } lbm_dtype;
 
 typedef enum {
@@ -59,6 +60,13 @@ typedef enum {
     LBM_ESTATE = -5,   /* call not valid in the current state (e.g. step before init) */
     LBM_ENUMERIC = -6  /* non-finite or non-positive density found by lbm_totals */
 } lbm_status;
+
+/* Step-kernel variants for a single box (lbm_set_kernel). */
+typedef enum {
+    LBM_KERNEL_AUTO = 0,      /* the scalar step unless a tuned choice was set */
+    LBM_KERNEL_SCALAR = 1,    /* one site per thread, 4/8-byte accesses */
+    LBM_KERNEL_ROW_WAVE = 2   /* V sites per lane, 8/16-byte accesses, x-neighbours by lane shuffle */
+} lbm_kernel;
 
 typedef struct {
     int32_t lattice, dtype;
@@ -72,11 +80,13 @@ typedef struct {
     uint64_t state_bytes;        /* bytes of one population buffer (see lbm_state_bytes) */
     int32_t block, grid;         /* launch shape in use (threads per block; batched grid size, 0 = one block per tile) */
     int32_t graph_chunk;         /* steps per captured graph */
+    int32_t kernel;              /* step kernel in use (lbm_kernel, never AUTO) */
 } lbm_info;
 
 /* Create a single periodic box (eq. lbe on an nx*ny*nz torus).
- * dims = {nx, ny, nz}, each >= 1; D2Q9 requires nz == 1.  Each of nx, ny, nz
- * and the total number of sites must be below 2^31.  tau: relaxation time,
+ * dims = {nx, ny, nz}, each >= 1; D2Q9 requires nz == 1.  nx and the total
+ * number of sites must be below 2^31, ny and nz at most 65535; in a batch
+ * every box holds less than 2 GiB of populations.  tau: relaxation time,
  * finite and > 1/2 (viscosity T0 (tau - 1/2)).  No device memory for the
  * populations is allocated until lbm_init / lbm_set_state, unless bound with
  * lbm_bind_state.  Errors: LBM_EINVAL, LBM_ENODEV, LBM_EDEVICE, LBM_ENOMEM. */
@@ -97,7 +107,11 @@ lbm_status lbm_set_hermite_order(lbm_t h, int32_t K);
  * The caller keeps ownership of the stream; it must outlive the handle's use. */
 lbm_status lbm_set_stream(lbm_t h, void* hip_stream);
 
-/* Bytes needed for one population buffer (Q planes, each padded to 256 bytes). */
+/* Bytes needed for one population buffer: Q * nsites stored values, rounded
+ * up to a multiple of 256.  Layout (row-tiled structure of arrays): box b
+ * holds elements [Q O_b, Q (O_b + n_b)), O_b its first global site; inside it
+ * x-row r = z * ny + y is a tile of Q * nx values with population i of site x
+ * at r * Q * nx + i * nx + x. */
 lbm_status lbm_state_bytes(lbm_t h, size_t* bytes_each);
 
 /* Use caller-owned device memory (e.g. two torch tensors) for the two
@@ -130,6 +144,13 @@ lbm_status lbm_set_graph_chunk(lbm_t h, int32_t steps);
  * block per tile).  Only before lbm_init. */
 lbm_status lbm_set_launch(lbm_t h, int32_t block, int32_t grid);
 
+/* Choose the single-box step kernel.  Both variants compute the same bits.
+ * LBM_KERNEL_ROW_WAVE needs nx to be a multiple of the sites per lane V (4 for
+ * FP32/FP16/BF16, 2 for FP64) with nx / V <= 64, and V above the largest
+ * velocity component (so FP64 D3Q39 has none); else LBM_EINVAL.  Batches
+ * always use the tiled batched kernel.  Only before lbm_init. */
+lbm_status lbm_set_kernel(lbm_t h, int32_t kernel);
+
 /* rho and u (eq. mme) of the current state, in float64, in the field layout
  * above.  on_device: as for lbm_init.  Synchronises. */
 lbm_status lbm_moments(lbm_t h, double* rho, double* u, int32_t on_device);
@@ -151,8 +172,10 @@ lbm_status lbm_residual(lbm_t h, const double* rho_ref, const double* u_ref, int
  * populations). */
 lbm_status lbm_checkpoint_bytes(lbm_t h, size_t* bytes);
 
-/* Copy the state (lattice, dtype, K, dims, t, and the stored deviations
- * g_i = f_i - w_i) to host memory `buf` of at least lbm_checkpoint_bytes(). */
+/* Copy the state to host memory `buf` of at least lbm_checkpoint_bytes(): a
+ * 64-byte header (lattice, dtype, K, geometry hash, t) followed by the stored
+ * values S (f_i - w_i) in the layout described at lbm_state_bytes (S = 36 for
+ * D2Q9 and D3Q19, 6480 for D3Q39). */
 lbm_status lbm_get_state(lbm_t h, void* buf, size_t bytes);
 
 /* Restore a state written by lbm_get_state on a handle of the same lattice,

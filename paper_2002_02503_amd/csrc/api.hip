@@ -69,7 +69,6 @@ struct lbm_ctx {
     std::vector<double> tau;        // nbox
     std::vector<int64_t> offset;    // nbox
     int64_t nsites = 0;
-    int64_t plane = 0;              // elements per population plane
     size_t elem = 0;                // bytes per stored population
     size_t state_bytes = 0;
     void* buf[2] = {nullptr, nullptr};
@@ -83,6 +82,7 @@ struct lbm_ctx {
     int device = 0;
     int block = 0;                  // 0 = automatic
     int grid = 0;                   // batched: 0 = one block per tile
+    int kernel = LBM_KERNEL_AUTO;   // single box: scalar or row-wave step
     int graph_chunk = kDefaultGraphChunk;
     // batched step tables
     TileDesc* d_tiles = nullptr;
@@ -103,6 +103,24 @@ struct lbm_ctx {
 namespace {
 
 bool is_single(const lbm_ctx* h) { return h->nbox == 1; }
+
+// Sites per lane when the row-wave step applies to this box (0 otherwise):
+// whole x-rows of nx = lanes_per_row * V sites with at most 64 lanes per row.
+int row_wave_sites(const lbm_ctx* h)
+{
+    if (!is_single(h)) return 0;
+    const int V = vec_sites_per_lane(h->lattice, h->dtype);
+    const int64_t nx = h->dims[0];
+    if (V == 0 || nx % V != 0 || nx / V > 64) return 0;
+    return V;
+}
+
+int effective_kernel(const lbm_ctx* h)
+{
+    if (!is_single(h)) return LBM_KERNEL_SCALAR;
+    if (h->kernel == LBM_KERNEL_AUTO) return LBM_KERNEL_SCALAR;  // measured faster unless tuned otherwise
+    return h->kernel;
+}
 
 int effective_block(const lbm_ctx* h)
 {
@@ -240,9 +258,21 @@ lbm_status create_common(lbm_t* out, int32_t lattice, int32_t nbox, const int64_
     }
     h->nsites = off;
     h->elem = storage_bytes(dtype);
-    const int64_t align = int64_t(256 / h->elem);
-    h->plane = ((h->nsites + align - 1) / align) * align;
-    h->state_bytes = size_t(h->plane) * size_t(L.Q) * h->elem;
+    // row-tiled layout: Q * nsites elements, allocation rounded to 256 bytes
+    h->state_bytes = ((size_t(h->nsites) * size_t(L.Q) * h->elem + 255) / 256) * 256;
+    if (nbox > 1)
+        for (int b = 0; b < nbox; ++b) {
+            const uint64_t nb = uint64_t(dims[3 * b]) * uint64_t(dims[3 * b + 1]) * uint64_t(dims[3 * b + 2]);
+            if (nb * uint64_t(L.Q) * h->elem >= (uint64_t(1) << 31)) {
+                delete h;
+                return fail(LBM_EINVAL, "box %d of a batch must hold less than 2 GiB of populations", b);
+            }
+        }
+    for (int b = 0; b < nbox; ++b)
+        if (dims[3 * b + 1] > 65535 || dims[3 * b + 2] > 65535) {
+            delete h;
+            return fail(LBM_EINVAL, "box %d: ny and nz must be at most 65535", b);
+        }
 
     auto cleanup = [&](lbm_status s) {
         free_all(h);
@@ -276,7 +306,7 @@ lbm_status create_common(lbm_t* out, int32_t lattice, int32_t nbox, const int64_
             hipSuccess)
         return cleanup(fail_hip(e, "copy reduction tables"));
 
-    if (nbox > 1) {
+    {
         std::vector<BoxDesc> boxes(nbox);
         for (int b = 0; b < nbox; ++b) {
             boxes[b].nx = int(dims[3 * b]);
@@ -320,17 +350,27 @@ hipError_t launch_one(lbm_ctx* h, int src_idx, hipStream_t s)
     const void* src = h->buf[src_idx];
     void* dst = h->buf[src_idx ^ 1];
     const int block = effective_block(h);
+    if (is_single(h) && effective_kernel(h) == LBM_KERNEL_ROW_WAVE) {
+        VecGeom geo;
+        const int V = row_wave_sites(h);
+        geo.nx = int(h->dims[0]);
+        geo.ny = int(h->dims[1]);
+        geo.nz = int(h->dims[2]);
+        geo.lanes_per_row = geo.nx / V;
+        geo.rows_per_wave = 64 / geo.lanes_per_row;
+        geo.nrows = geo.ny * geo.nz;
+        return launch_step_vec(h->lattice, h->dtype, h->K, src, dst, geo, 1.0 - 1.0 / h->tau[0], s);
+    }
     if (is_single(h)) {
         StepGeom geo;
         geo.nx = int(h->dims[0]);
         geo.ny = int(h->dims[1]);
         geo.nz = int(h->dims[2]);
         geo.xblocks = (geo.nx + block - 1) / block;
-        geo.plane = h->plane;
         return launch_step(h->lattice, h->dtype, h->K, src, dst, geo, 1.0 - 1.0 / h->tau[0], block, s);
     }
-    return launch_step_batch(h->lattice, h->dtype, h->K, src, dst, h->d_tiles, h->ntiles, h->d_boxes, h->plane,
-                             block, h->grid, s);
+    return launch_step_batch(h->lattice, h->dtype, h->K, src, dst, h->d_tiles, h->ntiles, h->d_boxes, block,
+                             h->grid, s);
 }
 
 lbm_status build_graph(lbm_ctx* h, int parity)
@@ -459,6 +499,19 @@ lbm_status lbm_set_launch(lbm_t h, int32_t block, int32_t grid)
     return LBM_OK;
 }
 
+lbm_status lbm_set_kernel(lbm_t h, int32_t kernel)
+{
+    if (lbm_status st = check_handle(h)) return st;
+    if (kernel != LBM_KERNEL_AUTO && kernel != LBM_KERNEL_SCALAR && kernel != LBM_KERNEL_ROW_WAVE)
+        return fail(LBM_EINVAL, "unknown kernel variant %d", kernel);
+    if (kernel == LBM_KERNEL_ROW_WAVE && !row_wave_sites(h))
+        return fail(LBM_EINVAL, "the row-wave step needs a single box with nx a multiple of the sites per lane "
+                                "and at most 64 lanes per row");
+    h->kernel = kernel;
+    drop_graphs(h);
+    return LBM_OK;
+}
+
 lbm_status lbm_init(lbm_t h, const double* rho, const double* u, int32_t on_device)
 {
     if (lbm_status st = check_handle(h)) return st;
@@ -474,7 +527,8 @@ lbm_status lbm_init(lbm_t h, const double* rho, const double* u, int32_t on_devi
         if (t1) (void)hipFree(drho);
         return st;
     }
-    hipError_t e = launch_init(h->lattice, h->dtype, h->K, drho, du, h->buf[0], h->nsites, h->plane, h->stream);
+    hipError_t e = launch_init(h->lattice, h->dtype, h->K, drho, du, h->buf[0], h->d_chunks, h->nchunks, h->d_boxes,
+                               h->nsites, h->stream);
     hipError_t e2 = hipStreamSynchronize(h->stream);
     if (t1) (void)hipFree(drho);
     if (t2) (void)hipFree(du);
@@ -537,7 +591,8 @@ lbm_status lbm_moments(lbm_t h, double* rho, double* u, int32_t on_device)
         HIP_TRY(hipMalloc(&drho, n * (1 + D) * sizeof(double)), "hipMalloc(moments)");
         du = drho + n;
     }
-    hipError_t e = launch_moments(h->lattice, h->dtype, h->buf[h->cur], drho, du, h->nsites, h->plane, h->stream);
+    hipError_t e = launch_moments(h->lattice, h->dtype, h->buf[h->cur], drho, du, h->d_chunks, h->nchunks, h->d_boxes,
+                                  h->nsites, h->stream);
     if (e == hipSuccess && !on_device) {
         e = hipMemcpyAsync(rho, drho, n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
         if (e == hipSuccess) e = hipMemcpyAsync(u, du, n * D * sizeof(double), hipMemcpyDeviceToHost, h->stream);
@@ -556,7 +611,7 @@ lbm_status lbm_totals(lbm_t h, double* out)
     if (!h->initialized) return fail(LBM_ESTATE, "lbm_totals before lbm_init");
     HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
     hipError_t e = launch_totals(h->lattice, h->dtype, h->buf[h->cur], h->d_chunks, h->nchunks,
-                                 h->d_box_chunk_begin, h->nbox, h->plane, h->d_partial, h->d_out, h->stream);
+                                 h->d_box_chunk_begin, h->nbox, h->d_boxes, h->d_partial, h->d_out, h->stream);
     if (e != hipSuccess) return fail_hip(e, "totals kernels");
     HIP_TRY(hipMemcpyAsync(out, h->d_out, size_t(h->nbox) * 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream),
             "copy totals");
@@ -584,7 +639,7 @@ lbm_status lbm_residual(lbm_t h, const double* rho_ref, const double* u_ref, int
         return st;
     }
     hipError_t e = launch_residual(h->lattice, h->dtype, h->buf[h->cur], dr, du, h->d_chunks, h->nchunks,
-                                   h->nsites, h->plane, h->d_partial, h->d_out, h->stream);
+                                   h->d_boxes, h->nsites, h->d_partial, h->d_out, h->stream);
     double tmp[4] = {0, 0, 0, 0};
     if (e == hipSuccess) e = hipMemcpyAsync(tmp, h->d_out, 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream);
     hipError_t e2 = hipStreamSynchronize(h->stream);
@@ -628,12 +683,9 @@ lbm_status lbm_get_state(lbm_t h, void* buf, size_t bytes)
     hd.payload_bytes = need - sizeof(CkptHeader);
     std::memcpy(buf, &hd, sizeof(hd));
     char* dst = static_cast<char*>(buf) + sizeof(hd);
-    const char* src = static_cast<const char*>(h->buf[h->cur]);
-    const size_t pb = size_t(h->nsites) * h->elem;
-    for (int i = 0; i < h->lat.Q; ++i)
-        HIP_TRY(hipMemcpyAsync(dst + i * pb, src + size_t(i) * size_t(h->plane) * h->elem, pb, hipMemcpyDeviceToHost,
-                               h->stream),
-                "copy state to host");
+    HIP_TRY(hipMemcpyAsync(dst, h->buf[h->cur], size_t(h->lat.Q) * size_t(h->nsites) * h->elem, hipMemcpyDeviceToHost,
+                           h->stream),
+            "copy state to host");
     HIP_TRY(hipStreamSynchronize(h->stream), "get_state synchronize");
     return LBM_OK;
 }
@@ -654,12 +706,9 @@ lbm_status lbm_set_state(lbm_t h, const void* buf, size_t bytes)
     if (lbm_status st = ensure_buffers(h)) return st;
     if (lbm_status st = build_tiles(h, effective_block(h))) return st;
     const char* src = static_cast<const char*>(buf) + sizeof(hd);
-    char* dst = static_cast<char*>(h->buf[0]);
-    const size_t pb = size_t(h->nsites) * h->elem;
-    for (int i = 0; i < h->lat.Q; ++i)
-        HIP_TRY(hipMemcpyAsync(dst + size_t(i) * size_t(h->plane) * h->elem, src + i * pb, pb, hipMemcpyHostToDevice,
-                               h->stream),
-                "copy state to device");
+    HIP_TRY(hipMemcpyAsync(h->buf[0], src, size_t(h->lat.Q) * size_t(h->nsites) * h->elem, hipMemcpyHostToDevice,
+                           h->stream),
+            "copy state to device");
     HIP_TRY(hipStreamSynchronize(h->stream), "set_state synchronize");
     h->cur = 0;
     h->t = hd.t;
@@ -688,6 +737,7 @@ lbm_status lbm_get_info(lbm_t h, lbm_info* info)
     info->block = effective_block(h);
     info->grid = h->grid;
     info->graph_chunk = h->graph_chunk;
+    info->kernel = effective_kernel(h);
     return LBM_OK;
 }
 

@@ -46,111 +46,185 @@
 
 namespace lbm {
 
+// Sparse dot products with compile-time integer coefficients: zero terms are
+// dropped and the sum starts from -0.0, which IEEE addition leaves unchanged,
+// so no "0 + x" or "0 * x" survives into the instruction stream.
+template <int X, int Y, int Z, class R>
+__device__ __forceinline__ R cdot(R ax, R ay, R az)
+{
+    R acc = R(-0.0);
+    if constexpr (X != 0) acc += R(X) * ax;
+    if constexpr (Y != 0) acc += R(Y) * ay;
+    if constexpr (Z != 0) acc += R(Z) * az;
+    return acc;
+}
+
+// c.q.c for a symmetric q given by its six components
+template <int X, int Y, int Z, class R>
+__device__ __forceinline__ R cquad(R qxx, R qyy, R qzz, R qxy, R qxz, R qyz)
+{
+    R acc = R(-0.0);
+    if constexpr (X != 0) acc += R(X * X) * qxx;
+    if constexpr (Y != 0) acc += R(Y * Y) * qyy;
+    if constexpr (Z != 0) acc += R(Z * Z) * qzz;
+    if constexpr (X * Y != 0) acc += R(2 * X * Y) * qxy;
+    if constexpr (X * Z != 0) acc += R(2 * X * Z) * qxz;
+    if constexpr (Y * Z != 0) acc += R(2 * Y * Z) * qyz;
+    return acc;
+}
+
 template <class L, int K, bool PROJ, class R>
 __device__ __forceinline__ void collide_site(R (&G)[L::Q], R omega)
 {
     static_assert(K >= 2 && K <= L::K_MAX, "Hermite order outside 2..2N-1");
+    constexpr int NP = (L::Q - 1) / 2;  // opposite pairs (2p+1, 2p+2)
+    constexpr bool D3 = (L::D == 3);
     constexpr R IT0 = R(L::INV_T0);
     constexpr R T0 = R(L::T0);
     constexpr R SR = R(L::S);
     constexpr R IS = R(1.0 / L::S);
+    constexpr R NZ = R(-0.0);
 
-    // zeroth, first and second moments (eq. mme, eq. Mflux), scaled by S
-    R sd = R(0), jx = R(0), jy = R(0), jz = R(0);
-    R sxx = R(0), syy = R(0), szz = R(0), sxy = R(0), sxz = R(0), syz = R(0);
-    unroll<L::Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
+    // zeroth, first and second moments (eq. mme, eq. Mflux), scaled by S,
+    // from pair sums s = G_+ + G_- and differences d = G_+ - G_-
+    R sd = G[0], jx = NZ, jy = NZ, jz = NZ;
+    R sxx = NZ, syy = NZ, szz = NZ, sxy = NZ, sxz = NZ, syz = NZ;
+    unroll<NP>([&](auto P) {
+        constexpr int i = 2 * decltype(P)::value + 1;
         constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
-        const R gi = G[i];
-        sd += gi;
-        if constexpr (cx != 0) jx += R(cx) * gi;
-        if constexpr (cy != 0) jy += R(cy) * gi;
-        if constexpr (cz != 0) jz += R(cz) * gi;
-        if constexpr (cx != 0) sxx += R(cx * cx) * gi;
-        if constexpr (cy != 0) syy += R(cy * cy) * gi;
-        if constexpr (cz != 0) szz += R(cz * cz) * gi;
-        if constexpr (cx * cy != 0) sxy += R(cx * cy) * gi;
-        if constexpr (cx * cz != 0) sxz += R(cx * cz) * gi;
-        if constexpr (cy * cz != 0) syz += R(cy * cz) * gi;
+        const R sp = G[i] + G[i + 1];
+        const R dp = G[i] - G[i + 1];
+        sd += sp;
+        if constexpr (cx != 0) jx += R(cx) * dp;
+        if constexpr (cy != 0) jy += R(cy) * dp;
+        if constexpr (cz != 0) jz += R(cz) * dp;
+        if constexpr (cx != 0) sxx += R(cx * cx) * sp;
+        if constexpr (cy != 0) syy += R(cy * cy) * sp;
+        if constexpr (cz != 0) szz += R(cz * cz) * sp;
+        if constexpr (cx * cy != 0) sxy += R(cx * cy) * sp;
+        if constexpr (cx * cz != 0) sxz += R(cx * cz) * sp;
+        if constexpr (cy * cz != 0) syz += R(cy * cz) * sp;
     });
 
     const R drho = sd / SR;
     const R rho = R(1) + drho;
-    const R rho_s = SR + sd;  // S rho
-    const R ux = jx / rho_s, uy = jy / rho_s, uz = jz / rho_s;
+    const R inv_rho_s = R(1) / (SR + sd);  // 1 / (S rho)
+    const R ux = jx * inv_rho_s, uy = jy * inv_rho_s;
+    const R uz = D3 ? jz * inv_rho_s : R(0);
 
-    // non-equilibrium momentum flux Pi = sum c c G / S - (rho-1) T0 I - rho u u
+    // non-equilibrium momentum flux Pi = sum c c G / S - (rho-1) T0 I - rho u u,
+    // kept as q = Pi / T0
     const R dT = drho * T0;
-    const R pxx = sxx * IS - dT - rho * ux * ux;
-    const R pyy = syy * IS - dT - rho * uy * uy;
-    const R pzz = (L::D == 3) ? szz * IS - dT - rho * uz * uz : R(0);
-    const R pxy = sxy * IS - rho * ux * uy;
-    const R pxz = (L::D == 3) ? sxz * IS - rho * ux * uz : R(0);
-    const R pyz = (L::D == 3) ? syz * IS - rho * uy * uz : R(0);
-    const R trP = pxx + pyy + pzz;
-    const R pux = pxx * ux + pxy * uy + pxz * uz;
-    const R puy = pxy * ux + pyy * uy + pyz * uz;
-    const R puz = pxz * ux + pyz * uy + pzz * uz;
-    const R Cs = (ux * pux + uy * puy + uz * puz) * IT0;
-    const R v = (ux * ux + uy * uy + uz * uz) * IT0;
+    const R qxx = (sxx * IS - dT - rho * ux * ux) * IT0;
+    const R qyy = (syy * IS - dT - rho * uy * uy) * IT0;
+    const R qxy = (sxy * IS - rho * ux * uy) * IT0;
+    R qzz = R(0), qxz = R(0), qyz = R(0);
+    if constexpr (D3) {
+        qzz = (szz * IS - dT - rho * uz * uz) * IT0;
+        qxz = (sxz * IS - rho * ux * uz) * IT0;
+        qyz = (syz * IS - rho * uy * uz) * IT0;
+    }
+
+    // site constants: a_i = c_i.uq, A_i = c_i.q.c_i - tr Pi, B_i = c_i.bq,
+    // C = u.Pi.u / T0, v = u.u / T0
+    const R uqx = ux * IT0, uqy = uy * IT0;
+    const R uqz = D3 ? uz * IT0 : R(0);
+    R v = ux * uqx + uy * uqy;
+    R trP = (qxx + qyy) * T0;
+    R bqx = qxx * ux + qxy * uy, bqy = qxy * ux + qyy * uy, bqz = R(0);
+    if constexpr (D3) {
+        v += uz * uqz;
+        trP = (qxx + qyy + qzz) * T0;
+        bqx += qxz * uz;
+        bqy += qyz * uz;
+        bqz = qxz * ux + qyz * uy + qzz * uz;
+    }
+    bqx *= R(2);
+    bqy *= R(2);
+    bqz *= R(2);
+    const R Cs = D3 ? R(0.5) * (ux * bqx + uy * bqy + uz * bqz) : R(0.5) * (ux * bqx + uy * bqy);
     const R om2 = omega * R(0.5) * IT0;
 
-    unroll<L::Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
+    // Each pair shares a, h_n and A; a, B and the odd h_n change sign under
+    // c -> -c.  With Pe / Po the even / odd parts of P_m = sum_{n<=m} h_n/n!,
+    //   N_even = A Pe_{K-2} - B Po_{K-3} + C Pe_{K-4},
+    //   N_odd  = A Po_{K-2} - B Pe_{K-3} + C Po_{K-4},
+    //   G_+- = W [(rho-1) + rho (Pe_K - 1) + om2 N_even] +- W [rho Po_K + om2 N_odd].
+    // Pe_0 = Pe_1 = 1, Pe_2 = Pe_3 = 1 + h2/2, Pe_4 = Pe_5 = Pe_2 + h4/24;
+    // Po_1 = Po_2 = a, Po_3 = Po_4 = a + h3/6, Po_5 = Po_3 + h5/120.
+    {
+        // rest particle: a = 0, B = 0, A = -tr Pi, h2 = -v, h3 = 0, h4 = 3 v^2
+        const R A0 = -trP;
+        const R Ee2 = R(-0.5) * v;
+        R Xe;
+        if constexpr (K <= 3) {
+            Xe = drho + rho * Ee2 + om2 * A0;
+        } else {
+            const R Ee4 = Ee2 + R(0.125) * v * v;
+            Xe = drho + rho * Ee4 + om2 * (A0 + A0 * Ee2 + Cs);
+        }
+        G[0] = R(L::W[0]) * Xe;
+    }
+    unroll<NP>([&](auto P) {
+        constexpr int i = 2 * decltype(P)::value + 1;
         constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
         constexpr R Wi = R(L::W[i]);
-        const R a = (R(cx) * ux + R(cy) * uy + R(cz) * uz) * IT0;
-        // scalar Hermite polynomials and their partial sums
-        const R h1 = a;
+        const R a = cdot<cx, cy, cz>(uqx, uqy, uqz);
+        const R A = cquad<cx, cy, cz>(qxx, qyy, qzz, qxy, qxz, qyz) - trP;
         const R h2 = a * a - v;
-        R h3 = R(0), h4 = R(0), h5 = R(0);
-        if constexpr (K >= 3) h3 = a * h2 - R(2) * v * h1;
-        if constexpr (K >= 4) h4 = a * h3 - R(3) * v * h2;
-        if constexpr (K >= 5) h5 = a * h4 - R(4) * v * h3;
-        // E_m = P_m - 1
-        const R E1 = h1;
-        const R E2 = E1 + h2 * R(0.5);
-        const R E3 = E2 + h3 * R(1.0 / 6.0);
-        const R E4 = E3 + h4 * R(1.0 / 24.0);
-        const R E5 = E4 + h5 * R(1.0 / 120.0);
-        R EK;
-        if constexpr (K == 2) EK = E2;
-        else if constexpr (K == 3) EK = E3;
-        else if constexpr (K == 4) EK = E4;
-        else EK = E5;
-        // A_i = c.Pi.c / T0 - tr Pi,  B_i = 2 c.Pi.u / T0
-        const R cPc = R(cx * cx) * pxx + R(cy * cy) * pyy + R(cz * cz) * pzz +
-                      R(2 * cx * cy) * pxy + R(2 * cx * cz) * pxz + R(2 * cy * cz) * pyz;
-        const R Ai = cPc * IT0 - trP;
-        const R Bi = R(2) * (R(cx) * pux + R(cy) * puy + R(cz) * puz) * IT0;
-        R N;
-        if constexpr (K == 2) N = Ai;
-        else if constexpr (K == 3) N = Ai * (R(1) + E1) - Bi;
-        else if constexpr (K == 4) N = Ai * (R(1) + E2) - Bi * (R(1) + E1) + Cs;
-        else N = Ai * (R(1) + E3) - Bi * (R(1) + E2) + Cs * (R(1) + E1);
-        G[i] = Wi * (drho * (R(1) + EK) + EK) + Wi * om2 * N;
+        const R Ee2 = R(0.5) * h2;
+        R Xe, Xo;
+        if constexpr (K == 2) {
+            Xe = drho + rho * Ee2 + om2 * A;
+            Xo = rho * a;
+        } else {
+            const R B = cdot<cx, cy, cz>(bqx, bqy, bqz);
+            const R h3 = a * (h2 - R(2) * v);
+            const R Po3 = a + R(1.0 / 6.0) * h3;
+            if constexpr (K == 3) {
+                Xe = drho + rho * Ee2 + om2 * A;
+                Xo = rho * Po3 + om2 * (A * a - B);
+            } else {
+                const R h4 = a * h3 - R(3) * v * h2;
+                const R Ee4 = Ee2 + R(1.0 / 24.0) * h4;
+                const R Ne = A + A * Ee2 - B * a + Cs;
+                Xe = drho + rho * Ee4 + om2 * Ne;
+                if constexpr (K == 4) {
+                    Xo = rho * Po3 + om2 * (A * a - B);
+                } else {
+                    const R h5 = a * h4 - R(4) * v * h3;
+                    const R Po5 = Po3 + R(1.0 / 120.0) * h5;
+                    Xo = rho * Po5 + om2 * (A * Po3 - B - B * Ee2 + Cs * a);
+                }
+            }
+        }
+        G[i] = Wi * (Xe + Xo);
+        G[i + 1] = Wi * (Xe - Xo);
     });
 
     if constexpr (PROJ) {
-        R m0 = R(0), mx = R(0), my = R(0), mz = R(0);
-        unroll<L::Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
+        R m0 = G[0], mx = NZ, my = NZ, mz = NZ;
+        unroll<NP>([&](auto P) {
+            constexpr int i = 2 * decltype(P)::value + 1;
             constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
-            const R gi = G[i];
-            m0 += gi;
-            if constexpr (cx != 0) mx += R(cx) * gi;
-            if constexpr (cy != 0) my += R(cy) * gi;
-            if constexpr (cz != 0) mz += R(cz) * gi;
+            const R dp = G[i] - G[i + 1];
+            m0 += G[i] + G[i + 1];
+            if constexpr (cx != 0) mx += R(cx) * dp;
+            if constexpr (cy != 0) my += R(cy) * dp;
+            if constexpr (cz != 0) mz += R(cz) * dp;
         });
         const R dm = (sd - m0) * IS;
         const R dx = (jx - mx) * (IS * IT0);
         const R dy = (jy - my) * (IS * IT0);
-        const R dz = (jz - mz) * (IS * IT0);
-        unroll<L::Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
+        const R dz = D3 ? (jz - mz) * (IS * IT0) : R(0);
+        G[0] += R(L::W[0]) * dm;
+        unroll<NP>([&](auto P) {
+            constexpr int i = 2 * decltype(P)::value + 1;
             constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
             constexpr R Wi = R(L::W[i]);
-            G[i] += Wi * (dm + R(cx) * dx + R(cy) * dy + R(cz) * dz);
+            const R cd = cdot<cx, cy, cz>(dx, dy, dz);
+            G[i] += Wi * (dm + cd);
+            G[i + 1] += Wi * (dm - cd);
         });
     }
 }

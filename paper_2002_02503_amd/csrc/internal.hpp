@@ -1,26 +1,41 @@
 // Library-internal declarations shared by the C-ABI implementation and the
 // kernel launchers.
+//
+// Population layout ("row-tiled structure of arrays").  Box b starts at site
+// offset O_b of the concatenated site space and holds nx * ny * nz sites.
+// Its populations occupy elements [Q O_b, Q (O_b + n_b)) of a buffer; inside
+// the box, x-row r = z * ny + y is one tile of Q * nx elements in which
+// population i of site x sits at r Q nx + i nx + x.  A row tile is thus a
+// small structure of arrays: every population row is contiguous in x, and a
+// step writes each tile as one contiguous run of Q * nx elements.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
-#include <map>
 #include <string>
-#include <utility>
 #include <vector>
 
 namespace lbm {
 
-// Geometry of a single box for the row-blocked step kernel.
+// Single box, one site per thread: grid (xblocks, ny, nz).
 struct StepGeom {
     int nx, ny, nz;
-    int xblocks;          // blocks per x row
-    long long plane;      // elements per population plane
+    int xblocks;          // blocks per x-row
 };
 
-// A tile of the batched step: `count` consecutive sites of one box, starting
-// at local site index `start` (count <= threads per block).
+// Single box, row-wave form: each lane owns V consecutive sites of an x-row,
+// a row takes lanes_per_row = nx / V lanes and a 64-lane wavefront holds
+// rows_per_wave = 64 / lanes_per_row rows.
+struct VecGeom {
+    int nx, ny, nz;
+    int lanes_per_row;
+    int rows_per_wave;
+    int nrows;            // ny * nz
+};
+
+// A tile of the batched step: up to blockDim.x consecutive sites of one box,
+// starting at the box-local site index `start`.
 struct TileDesc {
     int box;
     int start;
@@ -28,11 +43,12 @@ struct TileDesc {
 
 struct BoxDesc {
     int nx, ny, nz, pad;
-    long long offset;     // global index of the box's first site
+    long long offset;     // O_b: global index of the box's first site
     double omega;         // 1 - 1/tau
 };
 
-// A reduction chunk: `count` consecutive global sites belonging to one box.
+// A run of `count` consecutive global sites of one box (never two boxes),
+// the unit of the set-up, moment and reduction kernels.
 struct ChunkDesc {
     long long start;
     int count;
@@ -41,19 +57,24 @@ struct ChunkDesc {
 
 // Kernel launchers (kernels.hip).  All return hipSuccess or the first error.
 hipError_t launch_init(int lat, int dtype, int K, const double* rho, const double* u, void* dst,
-                       long long nsites, long long plane, hipStream_t s);
+                       const ChunkDesc* chunks, int nchunks, const BoxDesc* boxes, long long nsites,
+                       hipStream_t s);
 hipError_t launch_step(int lat, int dtype, int K, const void* src, void* dst, const StepGeom& geo,
                        double omega, int block, hipStream_t s);
+// Sites per lane of the row-wave kernel for (lattice, dtype), 0 if that pair
+// has no row-wave form (a velocity component as large as V).
+int vec_sites_per_lane(int lat, int dtype);
+hipError_t launch_step_vec(int lat, int dtype, int K, const void* src, void* dst, const VecGeom& geo, double omega,
+                           hipStream_t s);
 hipError_t launch_step_batch(int lat, int dtype, int K, const void* src, void* dst, const TileDesc* tiles,
-                             int ntiles, const BoxDesc* boxes, long long plane, int block, int grid,
-                             hipStream_t s);
-hipError_t launch_moments(int lat, int dtype, const void* src, double* rho, double* u, long long nsites,
-                          long long plane, hipStream_t s);
+                             int ntiles, const BoxDesc* boxes, int block, int grid, hipStream_t s);
+hipError_t launch_moments(int lat, int dtype, const void* src, double* rho, double* u, const ChunkDesc* chunks,
+                          int nchunks, const BoxDesc* boxes, long long nsites, hipStream_t s);
 hipError_t launch_totals(int lat, int dtype, const void* src, const ChunkDesc* chunks, int nchunks,
-                         const int* box_chunk_begin, int nbox, long long plane, double* partial,
-                         double* out, hipStream_t s);
+                         const int* box_chunk_begin, int nbox, const BoxDesc* boxes, double* partial, double* out,
+                         hipStream_t s);
 hipError_t launch_residual(int lat, int dtype, const void* src, const double* rho_ref, const double* u_ref,
-                           const ChunkDesc* chunks, int nchunks, long long nsites, long long plane,
+                           const ChunkDesc* chunks, int nchunks, const BoxDesc* boxes, long long nsites,
                            double* partial, double* out, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 

@@ -1,18 +1,17 @@
 // HIP kernels for gfx950 (MI355X): the fused pull-stream + collide step
-// (single box and batched), initialisation, moments, FP64 reductions and a
-// copy kernel used to calibrate bandwidth measurements.
+// (single box, one site per thread or row-wave; batches of boxes),
+// initialisation, moments, FP64 reductions and a copy kernel used to
+// calibrate bandwidth measurements.
 //
-// Data layout: structure of arrays.  Population i of site s lives at
-// buf[i * plane + s], s = (z * ny + y) * nx + x (x fastest); plane is the site
-// count rounded up so every plane starts on a 256-byte boundary.  Two buffers
-// alternate: a step reads one and writes the other, so a step never reads
-// what it writes.  The stored value is G_i = S (f_i - w_i), the deviation from
-// the rest weights in units of the lattice's weight quantum 1/S.
+// Data layout: row-tiled structure of arrays (see internal.hpp).  Two buffers
+// alternate: a step reads one and writes the other, so a step never reads what
+// it writes.  The stored value is G_i = S (f_i - w_i), the deviation from the
+// rest weights in units of the lattice's weight quantum 1/S.
 //
-// The step is bandwidth bound (about 600 flops against 2 Q S bytes per site,
-// far below the FP32 ridge of the chip), so it uses no matrix cores: one thread
-// per site, every population read once (pull form of eq. lbe, periodic wrap)
-// and written once, the collision entirely in registers.
+// The step is bandwidth bound (about 400 single-precision operations against
+// 2 Q S bytes per site, far below the FP32 ridge of the chip), so it uses no
+// matrix cores: every population is read once (pull form of eq. lbe, periodic
+// wrap) and written once, and the collision runs entirely in registers.
 #include <type_traits>
 
 #include "collide.hpp"
@@ -37,6 +36,7 @@ struct Store<double> {
     using R = double;
     static __device__ __forceinline__ R get(const double* p) { return *p; }
     static __device__ __forceinline__ void put(double* p, R v) { *p = v; }
+    static __device__ __forceinline__ void put_nt(double* p, R v) { __builtin_nontemporal_store(v, p); }
     static __device__ __forceinline__ void put_d(double* p, double v) { *p = v; }
 };
 
@@ -45,6 +45,7 @@ struct Store<float> {
     using R = float;
     static __device__ __forceinline__ R get(const float* p) { return *p; }
     static __device__ __forceinline__ void put(float* p, R v) { *p = v; }
+    static __device__ __forceinline__ void put_nt(float* p, R v) { __builtin_nontemporal_store(v, p); }
     static __device__ __forceinline__ void put_d(float* p, double v) { *p = float(v); }
 };
 
@@ -53,6 +54,7 @@ struct Store<_Float16> {
     using R = float;
     static __device__ __forceinline__ R get(const _Float16* p) { return float(*p); }
     static __device__ __forceinline__ void put(_Float16* p, R v) { *p = _Float16(v); }
+    static __device__ __forceinline__ void put_nt(_Float16* p, R v) { __builtin_nontemporal_store(_Float16(v), p); }
     static __device__ __forceinline__ void put_d(_Float16* p, double v) { *p = _Float16(v); }
 };
 
@@ -68,8 +70,22 @@ struct Store<bf16_t> {
         return uint16_t(u >> 16);
     }
     static __device__ __forceinline__ void put(bf16_t* p, R v) { p->bits = round_bf16(v); }
+    static __device__ __forceinline__ void put_nt(bf16_t* p, R v)
+    {
+        __builtin_nontemporal_store(round_bf16(v), reinterpret_cast<uint16_t*>(p));
+    }
     static __device__ __forceinline__ void put_d(bf16_t* p, double v) { p->bits = round_bf16(float(v)); }
 };
+
+// p + i for a uniform pointer p and a 32-bit element index i, with the byte
+// offset formed in 32 bits, so the access is a scalar base plus a 32-bit
+// vector offset.  Callers keep i * sizeof(T) below 4 GiB.
+template <class T>
+__device__ __forceinline__ T* at32(T* p, unsigned i)
+{
+    using B = std::conditional_t<std::is_const<T>::value, const char, char>;
+    return reinterpret_cast<T*>(reinterpret_cast<B*>(p) + unsigned(i * unsigned(sizeof(T))));
+}
 
 // Periodic wrap of a coordinate v in [-3, n + 2] onto [0, n).
 __device__ __forceinline__ int wrap_coord(int v, int n)
@@ -84,9 +100,11 @@ __device__ __forceinline__ int wrap_coord(int v, int n)
 }
 
 // ---------------------------------------------------------------------------
-// Fused step, single box.  One block covers `blockDim.x` sites of one x-row,
-// so y and z (and every y/z neighbour offset) are block-uniform scalars; only
-// the x wrap is per lane.
+// Fused step, single box, one site per thread.  The grid is (x-blocks, ny,
+// nz): a block covers blockDim.x sites of one x-row, so y, z and the source
+// row of every population are block-uniform; only the x wrap is per lane.
+// Every access is a uniform 64-bit pointer (row tile + population row) plus a
+// 32-bit lane offset.
 // ---------------------------------------------------------------------------
 
 template <class L, class S, int K>
@@ -98,13 +116,11 @@ __global__ __launch_bounds__(256) void k_step(const S* __restrict__ src, S* __re
     constexpr bool PROJ = !std::is_same<R, double>::value;
     constexpr int RR = L::R;
 
-    const int bid = blockIdx.x;
-    const int row = bid / geo.xblocks;
-    const int xb = bid - row * geo.xblocks;
-    const int y = row % geo.ny;
-    const int z = row / geo.ny;
-    const int x = xb * int(blockDim.x) + int(threadIdx.x);
+    const int y = blockIdx.y;
+    const int z = blockIdx.z;
+    const int x = int(blockIdx.x) * int(blockDim.x) + int(threadIdx.x);
     if (x >= geo.nx) return;
+    const long long tile = (long long)L::Q * geo.nx;  // elements per row tile
 
     int xw[2 * RR + 1], yw[2 * RR + 1], zw[2 * RR + 1];
 #pragma unroll
@@ -118,30 +134,209 @@ __global__ __launch_bounds__(256) void k_step(const S* __restrict__ src, S* __re
     unroll<L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
-        const long long rowoff = (long long)i * geo.plane +
-                                 ((long long)zw[RR - cz] * geo.ny + yw[RR - cy]) * (long long)geo.nx;
-        g[i] = ST::get(src + rowoff + xw[RR - cx]);
+        const int row = zw[RR - cz] * geo.ny + yw[RR - cy];
+        const S* p = src + row * tile + (long long)i * geo.nx;
+        g[i] = ST::get(at32(p, unsigned(xw[RR - cx])));
     });
 
     collide_site<L, K, PROJ, R>(g, omega);
 
-    const long long site = ((long long)z * geo.ny + y) * (long long)geo.nx + x;
+    S* q = dst + (long long)(z * geo.ny + y) * tile;
     unroll<L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        ST::put(dst + (long long)i * geo.plane + site, g[i]);
+        ST::put_nt(at32(q + (long long)i * geo.nx, unsigned(x)), g[i]);
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Fused step, single box, row-wave form.  Each wavefront owns whole x-rows;
+// each lane owns V consecutive sites of a row and moves them with one aligned
+// 8- or 16-byte access per population.  A population shifted along x by
+// c_x = +-1..3 (< V) needs V - |c_x| of its values from the lane itself and
+// |c_x| from the neighbouring lane of the same row (periodic within the row),
+// exchanged with a cross-lane shuffle instead of a second, misaligned load.
+// ---------------------------------------------------------------------------
+
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <class S, int V>
+struct VecIO;
+
+// V floats in 16 bytes
+template <>
+struct VecIO<float, 4> {
+    using VT = u32x4;
+    static __device__ __forceinline__ void unpack(VT w, float (&o)[4])
+    {
+        o[0] = __uint_as_float(w.x);
+        o[1] = __uint_as_float(w.y);
+        o[2] = __uint_as_float(w.z);
+        o[3] = __uint_as_float(w.w);
+    }
+    static __device__ __forceinline__ VT pack(const float (&v)[4])
+    {
+        VT w;
+        w.x = __float_as_uint(v[0]);
+        w.y = __float_as_uint(v[1]);
+        w.z = __float_as_uint(v[2]);
+        w.w = __float_as_uint(v[3]);
+        return w;
+    }
+};
+
+// V doubles in 16 bytes
+template <>
+struct VecIO<double, 2> {
+    using VT = u32x4;
+    static __device__ __forceinline__ void unpack(VT w, double (&o)[2])
+    {
+        o[0] = __hiloint2double(int(w.y), int(w.x));
+        o[1] = __hiloint2double(int(w.w), int(w.z));
+    }
+    static __device__ __forceinline__ VT pack(const double (&v)[2])
+    {
+        VT w;
+        w.x = uint32_t(__double2loint(v[0]));
+        w.y = uint32_t(__double2hiint(v[0]));
+        w.z = uint32_t(__double2loint(v[1]));
+        w.w = uint32_t(__double2hiint(v[1]));
+        return w;
+    }
+};
+
+// four 16-bit values in 8 bytes, FP16 or BF16
+template <class H>
+struct VecIO16 {
+    using VT = u32x2;
+    static __device__ __forceinline__ float half_to_float(uint32_t bits16)
+    {
+        if constexpr (std::is_same<H, bf16_t>::value) {
+            return __uint_as_float(bits16 << 16);
+        } else {
+            const uint16_t b = uint16_t(bits16);
+            return float(__builtin_bit_cast(_Float16, b));
+        }
+    }
+    static __device__ __forceinline__ uint32_t float_to_half(float v)
+    {
+        if constexpr (std::is_same<H, bf16_t>::value) {
+            return Store<bf16_t>::round_bf16(v);
+        } else {
+            return uint32_t(__builtin_bit_cast(uint16_t, _Float16(v)));
+        }
+    }
+    static __device__ __forceinline__ void unpack(VT w, float (&o)[4])
+    {
+        o[0] = half_to_float(w.x & 0xffffu);
+        o[1] = half_to_float(w.x >> 16);
+        o[2] = half_to_float(w.y & 0xffffu);
+        o[3] = half_to_float(w.y >> 16);
+    }
+    static __device__ __forceinline__ VT pack(const float (&v)[4])
+    {
+        VT w;
+        w.x = float_to_half(v[0]) | (float_to_half(v[1]) << 16);
+        w.y = float_to_half(v[2]) | (float_to_half(v[3]) << 16);
+        return w;
+    }
+};
+template <>
+struct VecIO<_Float16, 4> : VecIO16<_Float16> {};
+template <>
+struct VecIO<bf16_t, 4> : VecIO16<bf16_t> {};
+
+// Sites per lane of the row-wave kernel for each storage type.
+template <class S>
+constexpr int vec_sites()
+{
+    return std::is_same<S, double>::value ? 2 : 4;
+}
+
+template <class L, class S, int K>
+__global__ __launch_bounds__(256) void k_step_vec(const S* __restrict__ src, S* __restrict__ dst, VecGeom geo,
+                                                  typename Store<S>::R omega)
+{
+    using R = typename Store<S>::R;
+    constexpr int V = vec_sites<S>();
+    using IO = VecIO<S, V>;
+    using VT = typename IO::VT;
+    constexpr bool PROJ = !std::is_same<R, double>::value;
+    constexpr int RR = L::R;
+    static_assert(RR < V, "a shifted population must come from at most one neighbouring lane");
+
+    const int lane = int(threadIdx.x) & 63;
+    const int wave = int(blockIdx.x) * (int(blockDim.x) >> 6) + (int(threadIdx.x) >> 6);
+    const int lpr = geo.lanes_per_row;
+    const int r = lane / lpr;          // row within the wave
+    const int li = lane - r * lpr;     // lane within the row
+    const int row = wave * geo.rows_per_wave + r;
+    // Lanes past the last row of the wave, or past the last row of the box,
+    // leave now; every lane that stays only reads lanes of its own row.
+    if (r >= geo.rows_per_wave || row >= geo.nrows) return;
+    const int prev = r * lpr + (li == 0 ? lpr - 1 : li - 1);
+    const int next = r * lpr + (li == lpr - 1 ? 0 : li + 1);
+    const int y = row % geo.ny;
+    const int z = row / geo.ny;
+    const long long tile = (long long)L::Q * geo.nx;
+    int yw[2 * RR + 1], zw[2 * RR + 1];
+#pragma unroll
+    for (int k = 0; k <= 2 * RR; ++k) {
+        yw[k] = wrap_coord(y + k - RR, geo.ny);
+        zw[k] = wrap_coord(z + k - RR, geo.nz);
+    }
+
+    R g[V][L::Q];
+    unroll<L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
+        const long long srow = zw[RR - cz] * geo.ny + yw[RR - cy];
+        const S* p = src + srow * tile + (long long)i * geo.nx;
+        R own[V];
+        IO::unpack(*reinterpret_cast<const VT*>(p + (long long)li * V), own);
+        // site j pulls from x_j - c_x: element j - c_x of this lane when it is
+        // in [0, V), otherwise the wrapped element of the neighbouring lane
+        unroll<V>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            constexpr int e = j - cx;
+            if constexpr (e >= 0 && e < V) {
+                g[j][i] = own[e];
+            } else if constexpr (e < 0) {
+                g[j][i] = __shfl(own[e + V], prev, 64);
+            } else {
+                g[j][i] = __shfl(own[e - V], next, 64);
+            }
+        });
+    });
+
+    unroll<V>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        collide_site<L, K, PROJ, R>(g[j], omega);
+    });
+
+    S* q = dst + (long long)row * tile + (long long)li * V;
+    unroll<L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        R v[V];
+        unroll<V>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            v[j] = g[j][i];
+        });
+        __builtin_nontemporal_store(IO::pack(v), reinterpret_cast<VT*>(q + (long long)i * geo.nx));
     });
 }
 
 // ---------------------------------------------------------------------------
 // Fused step, batch of boxes.  A tile is up to blockDim.x consecutive sites
 // of one box; a fixed grid walks the tile table (grid-stride), so one launch
-// advances every box by one step.  Each box carries its own tau.
+// advances every box by one step.  Each box carries its own tau.  Offsets
+// inside a box fit 32 bits (checked on the host).
 // ---------------------------------------------------------------------------
 
 template <class L, class S, int K>
 __global__ __launch_bounds__(256) void k_step_batch(const S* __restrict__ src, S* __restrict__ dst,
                                                     const TileDesc* __restrict__ tiles, int ntiles,
-                                                    const BoxDesc* __restrict__ boxes, long long plane)
+                                                    const BoxDesc* __restrict__ boxes)
 {
     using ST = Store<S>;
     using R = typename ST::R;
@@ -158,6 +353,8 @@ __global__ __launch_bounds__(256) void k_step_batch(const S* __restrict__ src, S
         const int rem = local - z * nxy;
         const int y = rem / b.nx;
         const int x = rem - y * b.nx;
+        const S* sb = src + (long long)L::Q * b.offset;
+        S* db = dst + (long long)L::Q * b.offset;
 
         int xw[2 * RR + 1], yw[2 * RR + 1], zw[2 * RR + 1];
 #pragma unroll
@@ -170,32 +367,48 @@ __global__ __launch_bounds__(256) void k_step_batch(const S* __restrict__ src, S
         unroll<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
-            const int s = (zw[RR - cz] * b.ny + yw[RR - cy]) * b.nx + xw[RR - cx];
-            g[i] = ST::get(src + (long long)i * plane + b.offset + s);
+            const int srow = zw[RR - cz] * b.ny + yw[RR - cy];
+            g[i] = ST::get(at32(sb, unsigned((srow * L::Q + i) * b.nx + xw[RR - cx])));
         });
 
         collide_site<L, K, PROJ, R>(g, R(b.omega));
 
-        const long long site = b.offset + local;
+        const int row = z * b.ny + y;
         unroll<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            ST::put(dst + (long long)i * plane + site, g[i]);
+            ST::put_nt(at32(db, unsigned((row * L::Q + i) * b.nx + x)), g[i]);
         });
     }
 }
 
 // ---------------------------------------------------------------------------
-// Initialisation: f := f^eq_K(rho, u) (eq. hermite), evaluated in double and
-// rounded once to the storage type (set-up, not part of the step).
+// Set-up, moments and reductions work on chunks: runs of consecutive sites
+// of one box, one block per chunk.
 // ---------------------------------------------------------------------------
 
+// Element index of population 0 of a site, relative to the box's first
+// element: row tile r = local / nx, x = local % nx.
+__device__ __forceinline__ long long site_elem(long long local, int nx, int Q)
+{
+    const long long r = local / nx;
+    const long long x = local - r * nx;
+    return r * Q * nx + x;
+}
+
+// Initialisation: f := f^eq_K(rho, u) (eq. hermite), evaluated in double and
+// rounded once to the storage type (set-up, not part of the step).
 template <class L, class S, int K>
 __global__ __launch_bounds__(256) void k_init(const double* __restrict__ rho, const double* __restrict__ u,
-                                              S* __restrict__ dst, long long nsites, long long plane)
+                                              S* __restrict__ dst, const ChunkDesc* __restrict__ chunks,
+                                              const BoxDesc* __restrict__ boxes, long long nsites)
 {
     using ST = Store<S>;
-    for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < nsites;
-         s += (long long)gridDim.x * blockDim.x) {
+    const ChunkDesc ch = chunks[blockIdx.x];
+    const BoxDesc b = boxes[ch.box];
+    S* base = dst + (long long)L::Q * b.offset;
+    for (int k = threadIdx.x; k < ch.count; k += blockDim.x) {
+        const long long s = ch.start + k;
+        const long long e = site_elem(s - b.offset, b.nx, L::Q);
         const double ux = u[s];
         const double uy = u[nsites + s];
         const double uz = (L::D == 3) ? u[2 * nsites + s] : 0.0;
@@ -203,19 +416,15 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ rho, co
         equilibrium_scaled<L, K, double>(rho[s] - 1.0, ux, uy, uz, g);
         unroll<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            ST::put_d(dst + (long long)i * plane + s, g[i]);
+            ST::put_d(base + e + (long long)i * b.nx, g[i]);
         });
     }
 }
 
-// ---------------------------------------------------------------------------
-// Moments rho, u (eq. mme) of the stored state, in double (outside the step,
-// for output and reductions).
-// ---------------------------------------------------------------------------
-
+// rho - 1 and rho u (eq. mme) of one stored site, in double (outside the
+// step, for output and reductions).  `p` points at population 0 of the site.
 template <class L, class S>
-__device__ __forceinline__ void site_moments(const S* __restrict__ src, long long s, long long plane,
-                                             double& dsum, double (&j)[3])
+__device__ __forceinline__ void site_moments(const S* __restrict__ p, int nx, double& dsum, double (&j)[3])
 {
     using ST = Store<S>;
     dsum = 0.0;
@@ -223,7 +432,7 @@ __device__ __forceinline__ void site_moments(const S* __restrict__ src, long lon
     unroll<L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
-        const double gi = double(ST::get(src + (long long)i * plane + s));
+        const double gi = double(ST::get(p + (long long)i * nx));
         dsum += gi;
         if constexpr (cx != 0) j[0] += double(cx) * gi;
         if constexpr (cy != 0) j[1] += double(cy) * gi;
@@ -238,12 +447,16 @@ __device__ __forceinline__ void site_moments(const S* __restrict__ src, long lon
 
 template <class L, class S>
 __global__ __launch_bounds__(256) void k_moments(const S* __restrict__ src, double* __restrict__ rho,
-                                                 double* __restrict__ u, long long nsites, long long plane)
+                                                 double* __restrict__ u, const ChunkDesc* __restrict__ chunks,
+                                                 const BoxDesc* __restrict__ boxes, long long nsites)
 {
-    for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < nsites;
-         s += (long long)gridDim.x * blockDim.x) {
+    const ChunkDesc ch = chunks[blockIdx.x];
+    const BoxDesc b = boxes[ch.box];
+    const S* base = src + (long long)L::Q * b.offset;
+    for (int k = threadIdx.x; k < ch.count; k += blockDim.x) {
+        const long long s = ch.start + k;
         double d, j[3];
-        site_moments<L, S>(src, s, plane, d, j);
+        site_moments<L, S>(base + site_elem(s - b.offset, b.nx, L::Q), b.nx, d, j);
         const double r = 1.0 + d;
         rho[s] = r;
 #pragma unroll
@@ -281,13 +494,16 @@ __device__ __forceinline__ void block_tree(double (&acc)[NV], const bool (&is_ma
 template <class L, class S>
 __global__ __launch_bounds__(kRedBlock) void k_totals_partial(const S* __restrict__ src,
                                                               const ChunkDesc* __restrict__ chunks,
-                                                              long long plane, double* __restrict__ partial)
+                                                              const BoxDesc* __restrict__ boxes,
+                                                              double* __restrict__ partial)
 {
     const ChunkDesc ch = chunks[blockIdx.x];
+    const BoxDesc b = boxes[ch.box];
+    const S* base = src + (long long)L::Q * b.offset;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int k = threadIdx.x; k < ch.count; k += kRedBlock) {
         double d, j[3];
-        site_moments<L, S>(src, ch.start + k, plane, d, j);
+        site_moments<L, S>(base + site_elem(ch.start + k - b.offset, b.nx, L::Q), b.nx, d, j);
         acc[0] += d;
         acc[1] += j[0];
         acc[2] += j[1];
@@ -296,7 +512,7 @@ __global__ __launch_bounds__(kRedBlock) void k_totals_partial(const S* __restric
     const bool is_max[4] = {false, false, false, false};
     block_tree<4>(acc, is_max);
     if (threadIdx.x == 0) {
-        partial[blockIdx.x * 4 + 0] = double(ch.count) + acc[0];  // sum rho = sites + sum g
+        partial[blockIdx.x * 4 + 0] = double(ch.count) + acc[0];  // sum rho = sites + sum (rho - 1)
         partial[blockIdx.x * 4 + 1] = acc[1];
         partial[blockIdx.x * 4 + 2] = acc[2];
         partial[blockIdx.x * 4 + 3] = acc[3];
@@ -325,15 +541,17 @@ __global__ __launch_bounds__(kRedBlock) void k_residual_partial(const S* __restr
                                                                 const double* __restrict__ rho_ref,
                                                                 const double* __restrict__ u_ref,
                                                                 const ChunkDesc* __restrict__ chunks,
-                                                                long long nsites, long long plane,
-                                                                double* __restrict__ partial)
+                                                                const BoxDesc* __restrict__ boxes,
+                                                                long long nsites, double* __restrict__ partial)
 {
     const ChunkDesc ch = chunks[blockIdx.x];
+    const BoxDesc b = boxes[ch.box];
+    const S* base = src + (long long)L::Q * b.offset;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};  // max |du|, sum du^2, max |drho|, sum drho^2
     for (int k = threadIdx.x; k < ch.count; k += kRedBlock) {
         const long long s = ch.start + k;
         double d, j[3];
-        site_moments<L, S>(src, s, plane, d, j);
+        site_moments<L, S>(base + site_elem(s - b.offset, b.nx, L::Q), b.nx, d, j);
         const double r = 1.0 + d;
 #pragma unroll
         for (int a = 0; a < L::D; ++a) {
@@ -370,13 +588,13 @@ __global__ __launch_bounds__(kRedBlock) void k_residual_final(const double* __re
 }
 
 // ---------------------------------------------------------------------------
-// Plain 16-byte-vector copy, grid-stride.
+// Plain 16-byte-vector copy with non-temporal accesses, one vector per thread.
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, size_t n)
+__global__ __launch_bounds__(256) void k_copy(const u32x4* __restrict__ src, u32x4* __restrict__ dst, size_t n)
 {
-    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
-        dst[k] = src[k];
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) __builtin_nontemporal_store(__builtin_nontemporal_load(src + k), dst + k);
 }
 
 // ---------------------------------------------------------------------------
@@ -430,23 +648,14 @@ static hipError_t dispatch_ld(int lat, int dtype, F&& f)
     return dispatch(lat, dtype, 2, f);
 }
 
-static int grid_for(long long n, int block)
-{
-    long long g = (n + block - 1) / block;
-    const long long cap = 256LL * 64;  // enough blocks to fill 256 CUs many times over
-    if (g > cap) g = cap;
-    if (g < 1) g = 1;
-    return int(g);
-}
-
 hipError_t launch_init(int lat, int dtype, int K, const double* rho, const double* u, void* dst,
-                       long long nsites, long long plane, hipStream_t s)
+                       const ChunkDesc* chunks, int nchunks, const BoxDesc* boxes, long long nsites, hipStream_t s)
 {
     return dispatch(lat, dtype, K, [&](auto Lt, auto* Sp, auto Kc) -> hipError_t {
         using L = decltype(Lt);
         using S = std::remove_pointer_t<decltype(Sp)>;
         constexpr int KK = decltype(Kc)::value;
-        k_init<L, S, KK><<<grid_for(nsites, 256), 256, 0, s>>>(rho, u, static_cast<S*>(dst), nsites, plane);
+        k_init<L, S, KK><<<nchunks, 256, 0, s>>>(rho, u, static_cast<S*>(dst), chunks, boxes, nsites);
         return hipGetLastError();
     });
 }
@@ -459,16 +668,47 @@ hipError_t launch_step(int lat, int dtype, int K, const void* src, void* dst, co
         using S = std::remove_pointer_t<decltype(Sp)>;
         using R = typename Store<S>::R;
         constexpr int KK = decltype(Kc)::value;
-        const long long nblocks = (long long)geo.xblocks * geo.ny * geo.nz;
-        k_step<L, S, KK><<<dim3((unsigned)nblocks), block, 0, s>>>(static_cast<const S*>(src), static_cast<S*>(dst),
-                                                                   geo, R(omega));
+        k_step<L, S, KK><<<dim3(unsigned(geo.xblocks), unsigned(geo.ny), unsigned(geo.nz)), block, 0, s>>>(
+            static_cast<const S*>(src), static_cast<S*>(dst), geo, R(omega));
         return hipGetLastError();
     });
 }
 
+int vec_sites_per_lane(int lat, int dtype)
+{
+    int v = 0;
+    (void)dispatch(lat, dtype, 2, [&](auto Lt, auto* Sp, auto) -> hipError_t {
+        using L = decltype(Lt);
+        using S = std::remove_pointer_t<decltype(Sp)>;
+        constexpr int V = vec_sites<S>();
+        v = (L::R < V) ? V : 0;
+        return hipSuccess;
+    });
+    return v;
+}
+
+hipError_t launch_step_vec(int lat, int dtype, int K, const void* src, void* dst, const VecGeom& geo, double omega,
+                           hipStream_t s)
+{
+    return dispatch(lat, dtype, K, [&](auto Lt, auto* Sp, auto Kc) -> hipError_t {
+        using L = decltype(Lt);
+        using S = std::remove_pointer_t<decltype(Sp)>;
+        using R = typename Store<S>::R;
+        constexpr int KK = decltype(Kc)::value;
+        if constexpr (L::R < vec_sites<S>()) {
+            const long long waves = (geo.nrows + geo.rows_per_wave - 1) / geo.rows_per_wave;
+            const long long nblocks = (waves + 3) / 4;
+            k_step_vec<L, S, KK><<<dim3((unsigned)nblocks), 256, 0, s>>>(static_cast<const S*>(src),
+                                                                       static_cast<S*>(dst), geo, R(omega));
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;
+        }
+    });
+}
+
 hipError_t launch_step_batch(int lat, int dtype, int K, const void* src, void* dst, const TileDesc* tiles,
-                             int ntiles, const BoxDesc* boxes, long long plane, int block, int grid,
-                             hipStream_t s)
+                             int ntiles, const BoxDesc* boxes, int block, int grid, hipStream_t s)
 {
     return dispatch(lat, dtype, K, [&](auto Lt, auto* Sp, auto Kc) -> hipError_t {
         using L = decltype(Lt);
@@ -476,30 +716,30 @@ hipError_t launch_step_batch(int lat, int dtype, int K, const void* src, void* d
         constexpr int KK = decltype(Kc)::value;
         const int g = (grid > 0 && grid < ntiles) ? grid : ntiles;
         k_step_batch<L, S, KK><<<g, block, 0, s>>>(static_cast<const S*>(src), static_cast<S*>(dst), tiles, ntiles,
-                                                   boxes, plane);
+                                                   boxes);
         return hipGetLastError();
     });
 }
 
-hipError_t launch_moments(int lat, int dtype, const void* src, double* rho, double* u, long long nsites,
-                          long long plane, hipStream_t s)
+hipError_t launch_moments(int lat, int dtype, const void* src, double* rho, double* u, const ChunkDesc* chunks,
+                          int nchunks, const BoxDesc* boxes, long long nsites, hipStream_t s)
 {
     return dispatch_ld(lat, dtype, [&](auto Lt, auto* Sp, auto) -> hipError_t {
         using L = decltype(Lt);
         using S = std::remove_pointer_t<decltype(Sp)>;
-        k_moments<L, S><<<grid_for(nsites, 256), 256, 0, s>>>(static_cast<const S*>(src), rho, u, nsites, plane);
+        k_moments<L, S><<<nchunks, 256, 0, s>>>(static_cast<const S*>(src), rho, u, chunks, boxes, nsites);
         return hipGetLastError();
     });
 }
 
 hipError_t launch_totals(int lat, int dtype, const void* src, const ChunkDesc* chunks, int nchunks,
-                         const int* box_chunk_begin, int nbox, long long plane, double* partial, double* out,
+                         const int* box_chunk_begin, int nbox, const BoxDesc* boxes, double* partial, double* out,
                          hipStream_t s)
 {
     return dispatch_ld(lat, dtype, [&](auto Lt, auto* Sp, auto) -> hipError_t {
         using L = decltype(Lt);
         using S = std::remove_pointer_t<decltype(Sp)>;
-        k_totals_partial<L, S><<<nchunks, kRedBlock, 0, s>>>(static_cast<const S*>(src), chunks, plane, partial);
+        k_totals_partial<L, S><<<nchunks, kRedBlock, 0, s>>>(static_cast<const S*>(src), chunks, boxes, partial);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         k_totals_final<<<nbox, kRedBlock, 0, s>>>(partial, box_chunk_begin, out);
@@ -508,14 +748,14 @@ hipError_t launch_totals(int lat, int dtype, const void* src, const ChunkDesc* c
 }
 
 hipError_t launch_residual(int lat, int dtype, const void* src, const double* rho_ref, const double* u_ref,
-                           const ChunkDesc* chunks, int nchunks, long long nsites, long long plane,
+                           const ChunkDesc* chunks, int nchunks, const BoxDesc* boxes, long long nsites,
                            double* partial, double* out, hipStream_t s)
 {
     return dispatch_ld(lat, dtype, [&](auto Lt, auto* Sp, auto) -> hipError_t {
         using L = decltype(Lt);
         using S = std::remove_pointer_t<decltype(Sp)>;
         k_residual_partial<L, S><<<nchunks, kRedBlock, 0, s>>>(static_cast<const S*>(src), rho_ref, u_ref, chunks,
-                                                               nsites, plane, partial);
+                                                               boxes, nsites, partial);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         k_residual_final<<<1, kRedBlock, 0, s>>>(partial, nchunks, out);
@@ -526,10 +766,9 @@ hipError_t launch_residual(int lat, int dtype, const void* src, const double* rh
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s)
 {
     const size_t n = bytes / 16;
-    long long g = (long long)((n + 255) / 256);
-    if (g > 256LL * 32) g = 256LL * 32;
-    if (g < 1) g = 1;
-    k_copy<<<int(g), 256, 0, s>>>(static_cast<const uint4*>(src), static_cast<uint4*>(dst), n);
+    const size_t g = (n + 255) / 256;
+    if (g == 0 || g > 0x7fffffffu) return hipErrorInvalidValue;
+    k_copy<<<unsigned(g), 256, 0, s>>>(static_cast<const u32x4*>(src), static_cast<u32x4*>(dst), n);
     return hipGetLastError();
 }
 

@@ -13,6 +13,10 @@
 // any floating-point type.  The kernels keep the populations in these units
 // (see collide.hpp): no rounded weight ever enters the arithmetic.
 //
+// Velocity order.  The rest velocity comes first; every other velocity is
+// followed by its opposite (c_{2k} = -c_{2k-1}), so kernels can treat the
+// (Q-1)/2 pairs together.
+//
 // Every table is a compile-time constant.  Kernels index them only with
 // compile-time indices (through `unroll`), so each c_i component and weight is
 // folded into the instruction stream: zero components disappear and +/-1
@@ -44,8 +48,8 @@ struct D2Q9 {
     static constexpr int W[Q] = {16, 4, 4, 4, 4, 1, 1, 1, 1};
     static constexpr int8_t c[Q][3] = {
         {0, 0, 0},
-        {1, 0, 0}, {0, 1, 0}, {-1, 0, 0}, {0, -1, 0},
-        {1, 1, 0}, {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}};
+        {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0},
+        {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}};
     static constexpr double w[Q] = {
         4.0 / 9.0,
         1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
@@ -123,6 +127,18 @@ constexpr bool integer_weights_consistent()
     }
     return sum == L::S;
 }
+// Rest velocity first, then opposite pairs with equal weights.
+template <class L>
+constexpr bool opposite_pairs()
+{
+    if (L::c[0][0] != 0 || L::c[0][1] != 0 || L::c[0][2] != 0 || (L::Q % 2) != 1) return false;
+    for (int k = 1; k < L::Q; k += 2)
+        for (int a = 0; a < 3; ++a)
+            if (L::c[k + 1][a] != -L::c[k][a] || L::W[k + 1] != L::W[k]) return false;
+    return true;
+}
+static_assert(opposite_pairs<D2Q9>() && opposite_pairs<D3Q19>() && opposite_pairs<D3Q39>(), "pair order");
+
 static_assert(integer_weights_consistent<D2Q9>(), "D2Q9 weight quantum");
 static_assert(integer_weights_consistent<D3Q19>(), "D3Q19 weight quantum");
 static_assert(integer_weights_consistent<D3Q39>(), "D3Q39 weight quantum");

@@ -19,13 +19,14 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 LATTICES = {"D2Q9": 0, "D3Q19": 1, "D3Q39": 2}
 DTYPES = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
 DTYPE_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2}
+KERNELS = {"auto": 0, "scalar": 1, "row_wave": 2}
 STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE", -4: "LBM_ENODEV",
           -5: "LBM_ESTATE", -6: "LBM_ENUMERIC"}
 
 # Every entry point declared in include/lbm.h.
 EXPORTS = ["lbm_create", "lbm_create_batch", "lbm_set_hermite_order", "lbm_set_stream", "lbm_state_bytes",
            "lbm_bind_state", "lbm_init", "lbm_step", "lbm_prepare", "lbm_set_graph_chunk", "lbm_set_launch",
-           "lbm_moments", "lbm_totals", "lbm_residual", "lbm_checkpoint_bytes", "lbm_get_state",
+           "lbm_set_kernel", "lbm_moments", "lbm_totals", "lbm_residual", "lbm_checkpoint_bytes", "lbm_get_state",
            "lbm_set_state", "lbm_get_info", "lbm_sync", "lbm_destroy", "lbm_last_error", "lbm_lattice_table",
            "lbm_copy_probe"]
 
@@ -43,7 +44,7 @@ class lbm_info(ctypes.Structure):
                 ("T0", ctypes.c_double), ("nbox", ctypes.c_int32), ("dims", ctypes.c_int64 * 3),
                 ("nsites", ctypes.c_int64), ("t", ctypes.c_int64), ("bytes_per_site_update", ctypes.c_int64),
                 ("state_bytes", ctypes.c_uint64), ("block", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("graph_chunk", ctypes.c_int32)]
+                ("graph_chunk", ctypes.c_int32), ("kernel", ctypes.c_int32)]
 
 
 _lib = None
@@ -72,6 +73,7 @@ def load_library() -> ctypes.CDLL:
         "lbm_prepare": [vp],
         "lbm_set_graph_chunk": [vp, ctypes.c_int32],
         "lbm_set_launch": [vp, ctypes.c_int32, ctypes.c_int32],
+        "lbm_set_kernel": [vp, ctypes.c_int32],
         "lbm_moments": [vp, vp, vp, ctypes.c_int32],
         "lbm_totals": [vp, dp],
         "lbm_residual": [vp, vp, vp, ctypes.c_int32, dp],
@@ -145,7 +147,7 @@ class Simulation:
 
     def __init__(self, lattice: str, dims, tau, dtype: str = "fp32", K: int | None = None,
                  block: int = 0, grid: int = 0, graph_chunk: int | None = None, torch_memory: bool = True,
-                 stream=None):
+                 stream=None, kernel: str = "auto"):
         self.lib = load_library()
         self.lattice = lattice
         self.dtype = dtype
@@ -172,6 +174,8 @@ class Simulation:
                 _check(self.lib.lbm_set_launch(self.h, int(block), int(grid)))
             if graph_chunk is not None:
                 _check(self.lib.lbm_set_graph_chunk(self.h, int(graph_chunk)))
+            if kernel != "auto":
+                _check(self.lib.lbm_set_kernel(self.h, KERNELS[kernel]))
             torch = _torch()
             if stream is None:
                 stream = torch.cuda.current_stream()

@@ -33,11 +33,11 @@ def test_d2q9_taylor_green_fp64():
     assert abs(ratio / np.exp(-2 * (tau - 0.5) / 3 * k * k * steps) - 1) < 2e-3
 
 
-def _shear_gpu(lattice, dims, tau, U, steps, dtype="fp32", every=100):
+def _shear_gpu(lattice, dims, tau, U, steps, dtype="fp32", every=100, K=None):
     nx = dims[0]
     rho, u = inputs.shear_wave(dims, 0.01, U)
     ts, amps = [0], [mode_amplitude(u[1, 0, 0] - U[1], nx, axis=0)]
-    with lbm.Simulation(lattice, dims, tau, dtype=dtype) as sim:
+    with lbm.Simulation(lattice, dims, tau, dtype=dtype, K=K) as sim:
         sim.init(rho, u)
         for t in range(every, steps + 1, every):
             sim.step(every)
@@ -47,10 +47,27 @@ def _shear_gpu(lattice, dims, tau, U, steps, dtype="fp32", every=100):
     return r, uu, np.array(ts), np.array(amps)
 
 
+def _shear_oracle_rate(lattice, nx, tau, U, steps, every=100, K=None):
+    sim = oracle.Sim(lattice, (nx, 1, 1), tau, K=K)
+    rho, u = inputs.shear_wave((nx, 1, 1), 0.01, U)
+    sim.init(rho, u)
+    ts, amps = [0], [mode_amplitude(u[1, 0, 0] - U[1], nx, axis=0)]
+    for t in range(every, steps + 1, every):
+        sim.step(every)
+        _, uu = sim.moments()
+        ts.append(t)
+        amps.append(mode_amplitude(uu[1, 0, 0] - U[1], nx, axis=0))
+    return fit_decay(ts, amps)
+
+
 def test_d3q19_shear_wave_128_fp32():
     """D3Q19, 128^3, FP32, tau = 0.55, shear wave 0.01 on U = (0.1, 0.05, 0),
-    2000 steps: parity with the oracle, x-only structure kept bit for bit, and
-    the decay rate unchanged by U (Galilean test) to the oracle's accuracy."""
+    2000 steps: parity with the oracle, x-only structure kept bit for bit, the
+    decay rate equal to the oracle's, and the Galilean test at full size: the
+    paper's operator (K = 3) keeps the decay rate of the U = 0 run far better
+    than the zero-velocity filter (K = 2).  (The absolute Galilean error of the
+    paper's operator, ~1e-5, is pinned on the oracle; over this horizon the
+    wave decays by only 8%, so FP32 rounding limits a rate fit to ~1e-4.)"""
     n, tau, steps, U = 128, 0.55, 2000, (0.1, 0.05, 0.0)
     r, uu, ts, amps = _shear_gpu("D3Q19", (n, n, n), tau, U, steps)
     # the field depends on x only, bit for bit
@@ -61,10 +78,22 @@ def test_d3q19_shear_wave_128_fp32():
     eu, er = rel_u(uu[:, :1, :1, :], u_ref), rel_rho(r[:1, :1, :], r_ref)
     print(f"D3Q19 128^3 shear fp32: u {eu:.2e} rho {er:.2e}", flush=True)
     assert eu < 1e-5 and er < 1e-5
-    _, _, ts0, amps0 = _shear_gpu("D3Q19", (n, n, n), tau, (0.0, 0.0, 0.0), steps)
-    gal = fit_decay(ts, amps) / fit_decay(ts0, amps0) - 1
-    print(f"D3Q19 Galilean error (GPU): {gal:.2e}", flush=True)
-    assert abs(gal) < 1e-4
+    g_gpu = fit_decay(ts, amps)
+    g_ora = _shear_oracle_rate("D3Q19", n, tau, U, steps)
+    print(f"decay rate GPU {g_gpu:.6e} oracle {g_ora:.6e}", flush=True)
+    assert abs(g_gpu / g_ora - 1) < 1e-3
+    gal = {}
+    for K in [3, 2]:
+        if K == 3:
+            tU, aU = ts, amps
+        else:
+            _, _, tU, aU = _shear_gpu("D3Q19", (n, n, n), tau, U, steps, K=K)
+        _, _, t0, a0 = _shear_gpu("D3Q19", (n, n, n), tau, (0.0, 0.0, 0.0), steps, K=K)
+        gal[K] = abs(fit_decay(tU, aU) / fit_decay(t0, a0) - 1)
+    print(f"Galilean error on the GPU, U = (0.1, 0.05, 0): K=3 {gal[3]:.2e}, K=2 (old filter) {gal[2]:.2e}",
+          flush=True)
+    assert gal[2] > 1e-2
+    assert gal[3] < 1e-3 and gal[3] < gal[2] / 20
 
 
 def test_d3q39_shear_wave_192_fp32():
