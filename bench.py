@@ -60,11 +60,18 @@ def timed_steps(sim, steps: int, warmup: int) -> float:
     return e0.elapsed_time(e1) / steps
 
 
-def measure_box(lattice, dims, tau, dtype, rho, u, steps, warmup, **kw):
+KERNEL_NAMES = {1: "scalar", 2: "row_wave"}
+
+
+def measure_box(lattice, dims, tau, dtype, rho, u, steps, warmup, tune=True, **kw):
+    """Create, initialise, autotune the launch (outside the timed region, state
+    restored), then time `steps` steps."""
     from paper_2002_02503_amd import lbm
 
     with lbm.Simulation(lattice, dims, tau, dtype=dtype, **kw) as sim:
         sim.init(rho, u)
+        if tune:
+            sim.tune(steps=10)
         ms = timed_steps(sim, steps, warmup)
         info = sim.info()
     bytes_site = info["bytes_per_site_update"]
@@ -73,7 +80,8 @@ def measure_box(lattice, dims, tau, dtype, rho, u, steps, warmup, **kw):
     gbs = bytes_site * nsites / (ms * 1e-3) / 1e9
     return {"value": mlups, "unit": "MLUPS", "ms_per_step": ms, "steps": steps,
             "bytes_per_site_update": bytes_site, "nsites": nsites, "achieved_GBs": gbs,
-            "roofline_frac": gbs / PEAK_HBM_GBS, "block": info["block"]}
+            "roofline_frac": gbs / PEAK_HBM_GBS, "kernel": KERNEL_NAMES[info["kernel"]],
+            "block": info["block"], "grid": info["grid"]}
 
 
 def traffic_per_launch():
@@ -155,6 +163,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle leg (CPU baseline timing and error statements)")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle stepping")
+    ap.add_argument("--kernel", choices=["tune", "scalar", "row_wave"], default="tune",
+                    help="headline step kernel: autotuned (default) or pinned")
+    ap.add_argument("--block", type=int, default=256, help="threads per block when --kernel is pinned")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -173,13 +184,19 @@ def main():
     rho, u = inputs.turbulence(256)
 
     log(f"FP32 256^3: {args.warmup} warm-up + {args.steps} timed steps")
-    head = measure_box("D3Q19", (256, 256, 256), tau, "fp32", rho, u, args.steps, args.warmup)
+    if args.kernel == "tune":
+        head = measure_box("D3Q19", (256, 256, 256), tau, "fp32", rho, u, args.steps, args.warmup)
+    else:
+        pin = {"kernel": args.kernel, "block": args.block if args.kernel == "scalar" else 0}
+        head = measure_box("D3Q19", (256, 256, 256), tau, "fp32", rho, u, args.steps, args.warmup, tune=False, **pin)
+    log(f"headline: {head['value']:.0f} MLUPS with the {head['kernel']} step, block {head['block']}")
     nsites = head["nsites"]
     traffic, traffic_src = traffic_per_launch()
     roofline = {"bound": "hbm", "achieved": head["achieved_GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": head["achieved_GBs"] / PEAK_HBM_GBS, "traffic": traffic,
                 "algorithmic_bytes_per_launch": head["bytes_per_site_update"] * nsites,
-                "kernel": "k_step<D3Q19, float, K=3>", "traffic_source": traffic_src}
+                "kernel": ("k_step" if head["kernel"] == "scalar" else "k_step_vec") + "<D3Q19, float, K=3>",
+                "launch": {"kernel": head["kernel"], "block": head["block"]}, "traffic_source": traffic_src}
 
     log("copy probe at the same footprint")
     copy_bytes = head["bytes_per_site_update"] // 2 * nsites

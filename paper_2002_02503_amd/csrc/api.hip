@@ -9,7 +9,10 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -575,6 +578,128 @@ lbm_status lbm_step(lbm_t h, int64_t n)
         h->cur ^= 1;
         h->t += 1;
     }
+    return LBM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct LaunchChoice {
+    int kernel, block, grid;
+};
+
+std::string tune_key(const lbm_ctx* h)
+{
+    char buf[256];
+    snprintf(buf, sizeof(buf), "lattice=%d dtype=%d K=%d nbox=%d nsites=%lld geometry=%016llx", h->lattice,
+             h->dtype, h->K, h->nbox, (long long)h->nsites, (unsigned long long)geometry_hash(h));
+    return buf;
+}
+
+bool cache_lookup(const char* path, const std::string& key, LaunchChoice* out)
+{
+    if (!path || !*path) return false;
+    std::ifstream in(path);
+    std::string line;
+    bool found = false;
+    while (std::getline(in, line)) {
+        const size_t bar = line.find(" | ");
+        if (bar == std::string::npos || line.compare(0, bar, key) != 0 || bar != key.size()) continue;
+        std::istringstream rest(line.substr(bar + 3));
+        LaunchChoice c;
+        if (rest >> c.kernel >> c.block >> c.grid) {
+            *out = c;  // the last entry for a key wins
+            found = true;
+        }
+    }
+    return found;
+}
+
+void cache_store(const char* path, const std::string& key, const LaunchChoice& c)
+{
+    if (!path || !*path) return;
+    std::ofstream out(path, std::ios::app);
+    out << key << " | " << c.kernel << " " << c.block << " " << c.grid << "\n";
+}
+
+void apply_choice(lbm_ctx* h, const LaunchChoice& c)
+{
+    h->kernel = c.kernel;
+    h->block = c.block;
+    h->grid = c.grid;
+    drop_graphs(h);
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_tune(lbm_t h, int32_t steps, const char* cache_path)
+{
+    if (lbm_status st = check_handle(h)) return st;
+    if (steps < 1) return fail(LBM_EINVAL, "steps must be >= 1");
+    if (!h->initialized) return fail(LBM_ESTATE, "lbm_tune needs an initialised state");
+    if (!cache_path) cache_path = std::getenv("LBM_TUNE_CACHE");
+    const std::string key = tune_key(h);
+    LaunchChoice best;
+    if (cache_lookup(cache_path, key, &best)) {
+        if (best.kernel == LBM_KERNEL_ROW_WAVE && !row_wave_sites(h)) best.kernel = LBM_KERNEL_SCALAR;
+        apply_choice(h, best);
+        return LBM_OK;
+    }
+    HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+
+    std::vector<LaunchChoice> cand;
+    if (is_single(h)) {
+        for (int b : {64, 128, 256}) cand.push_back({LBM_KERNEL_SCALAR, b, 0});
+        if (row_wave_sites(h)) cand.push_back({LBM_KERNEL_ROW_WAVE, 0, 0});
+    } else {
+        for (int b : {64, 128, 256})
+            for (int g : {0, 1024, 2048, 4096}) cand.push_back({LBM_KERNEL_SCALAR, b, g});
+    }
+
+    // tuning steps the state: keep a copy and restore it afterwards
+    const int cur0 = h->cur;
+    const int64_t t0 = h->t;
+    const LaunchChoice old = {h->kernel, h->block, h->grid};
+    void* saved = nullptr;
+    HIP_TRY(hipMalloc(&saved, h->state_bytes), "hipMalloc(tuning copy)");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMemcpyAsync(saved, h->buf[cur0], h->state_bytes, hipMemcpyDeviceToDevice, h->stream);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    lbm_status st = (e == hipSuccess) ? LBM_OK : fail_hip(e, "tuning set-up");
+    float best_ms = 0.f;
+    for (size_t k = 0; k < cand.size() && st == LBM_OK; ++k) {
+        apply_choice(h, cand[k]);
+        if ((st = lbm_step(h, 2)) != LBM_OK) break;
+        if ((e = hipEventRecord(e0, h->stream)) != hipSuccess) { st = fail_hip(e, "hipEventRecord"); break; }
+        if ((st = lbm_step(h, steps)) != LBM_OK) break;
+        if ((e = hipEventRecord(e1, h->stream)) != hipSuccess) { st = fail_hip(e, "hipEventRecord"); break; }
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) { st = fail_hip(e, "hipEventSynchronize"); break; }
+        float ms = 0.f;
+        if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) { st = fail_hip(e, "hipEventElapsedTime"); break; }
+        if (k == 0 || ms < best_ms) {
+            best_ms = ms;
+            best = cand[k];
+        }
+    }
+    // restore the state whatever happened
+    hipError_t re = hipMemcpyAsync(h->buf[cur0], saved, h->state_bytes, hipMemcpyDeviceToDevice, h->stream);
+    if (re == hipSuccess) re = hipStreamSynchronize(h->stream);
+    (void)hipFree(saved);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    h->cur = cur0;
+    h->t = t0;
+    if (st != LBM_OK) {
+        apply_choice(h, old);
+        return st;
+    }
+    if (re != hipSuccess) return fail_hip(re, "restoring the state after tuning");
+    apply_choice(h, best);
+    cache_store(cache_path, key, best);
     return LBM_OK;
 }
 

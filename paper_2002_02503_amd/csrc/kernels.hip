@@ -62,12 +62,10 @@ template <>
 struct Store<bf16_t> {
     using R = float;
     static __device__ __forceinline__ R get(const bf16_t* p) { return __uint_as_float(uint32_t(p->bits) << 16); }
+    // round to nearest even (gfx950 converts in one instruction)
     static __device__ __forceinline__ uint16_t round_bf16(float v)
     {
-        uint32_t u = __float_as_uint(v);
-        if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40u);  // quiet NaN
-        u += 0x7fffu + ((u >> 16) & 1u);
-        return uint16_t(u >> 16);
+        return __builtin_bit_cast(uint16_t, static_cast<__bf16>(v));
     }
     static __device__ __forceinline__ void put(bf16_t* p, R v) { p->bits = round_bf16(v); }
     static __device__ __forceinline__ void put_nt(bf16_t* p, R v)

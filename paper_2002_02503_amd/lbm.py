@@ -26,7 +26,7 @@ STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE", -4
 # Every entry point declared in include/lbm.h.
 EXPORTS = ["lbm_create", "lbm_create_batch", "lbm_set_hermite_order", "lbm_set_stream", "lbm_state_bytes",
            "lbm_bind_state", "lbm_init", "lbm_step", "lbm_prepare", "lbm_set_graph_chunk", "lbm_set_launch",
-           "lbm_set_kernel", "lbm_moments", "lbm_totals", "lbm_residual", "lbm_checkpoint_bytes", "lbm_get_state",
+           "lbm_set_kernel", "lbm_tune", "lbm_moments", "lbm_totals", "lbm_residual", "lbm_checkpoint_bytes", "lbm_get_state",
            "lbm_set_state", "lbm_get_info", "lbm_sync", "lbm_destroy", "lbm_last_error", "lbm_lattice_table",
            "lbm_copy_probe"]
 
@@ -74,6 +74,7 @@ def load_library() -> ctypes.CDLL:
         "lbm_set_graph_chunk": [vp, ctypes.c_int32],
         "lbm_set_launch": [vp, ctypes.c_int32, ctypes.c_int32],
         "lbm_set_kernel": [vp, ctypes.c_int32],
+        "lbm_tune": [vp, ctypes.c_int32, ctypes.c_char_p],
         "lbm_moments": [vp, vp, vp, ctypes.c_int32],
         "lbm_totals": [vp, dp],
         "lbm_residual": [vp, vp, vp, ctypes.c_int32, dp],
@@ -238,6 +239,12 @@ class Simulation:
 
     def prepare(self):
         _check(self.lib.lbm_prepare(self.h))
+        return self
+
+    def tune(self, steps: int = 20, cache: str | None = None):
+        """Time the candidate launch shapes / step kernels and keep the fastest
+        (the state is restored afterwards); `cache` is an optional text file."""
+        _check(self.lib.lbm_tune(self.h, int(steps), cache.encode() if cache else None))
         return self
 
     def sync(self):

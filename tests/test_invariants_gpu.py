@@ -194,3 +194,44 @@ def test_batch_of_equal_boxes_equals_single_boxes():
         r, uu = sim.moments()
     for k, ub in enumerate(sim.split_boxes(uu)):
         assert np.abs(ub - single[1]).max() < 1e-7, k
+
+
+@pytest.mark.parametrize("lattice,dims,dtype", [("D3Q19", (64, 12, 10), "fp32"), ("D3Q19", (64, 12, 10), "bf16"),
+                                                ("D3Q39", (48, 9, 7), "fp32")])
+def test_tuning_restores_state_and_keeps_results(lattice, dims, dtype, tmp_path):
+    """lbm_tune times every candidate launch on the live state, restores it,
+    and whatever it picks computes the same bits; its cache is reused."""
+    rho, u = _fields(dims, 11)
+    ref = run_gpu(lattice, dims, 0.6, dtype, rho, u, 30)
+    cache = str(tmp_path / "tune.txt")
+    with lbm.Simulation(lattice, dims, 0.6, dtype=dtype) as sim:
+        sim.init(rho, u).step(10)
+        sim.tune(steps=5, cache=cache)
+        assert sim.t == 10
+        chosen = sim.info()
+        sim.step(20)
+        r, uu = sim.moments()
+    assert np.array_equal(r, ref[0]) and np.array_equal(uu, ref[1])
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1
+    with lbm.Simulation(lattice, dims, 0.6, dtype=dtype) as sim2:
+        sim2.init(rho, u).tune(steps=5, cache=cache)
+        info = sim2.info()
+        assert (info["kernel"], info["block"]) == (chosen["kernel"], chosen["block"])
+    assert len(open(cache).read().splitlines()) == 1
+
+
+def test_tuning_a_batch_keeps_results(tmp_path):
+    dims = [(20, 17, 9), (33, 8, 12), (16, 16, 16)]
+    rng = np.random.default_rng(12)
+    n = sum(a * b * c for a, b, c in dims)
+    rho = 1 + rng.uniform(-0.01, 0.01, n)
+    u = rng.uniform(-0.05, 0.05, (3, n))
+    with lbm.Simulation("D3Q19", dims, [0.6, 0.7, 0.8], dtype="fp32") as a:
+        a.init(rho, u).step(25)
+        ra, ua = a.moments()
+    with lbm.Simulation("D3Q19", dims, [0.6, 0.7, 0.8], dtype="fp32") as b:
+        b.init(rho, u).tune(steps=4, cache=str(tmp_path / "c.txt")).step(25)
+        rb, ub = b.moments()
+        assert b.info()["block"] in (64, 128, 256)
+    assert np.array_equal(ra, rb) and np.array_equal(ua, ub)
