@@ -27,7 +27,8 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS & % HBM roofline, D3Q19 256³ FP32 vs FP16-storage at stated error"
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E peak
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_d3q19_256_fp32.json")
-KERNEL_SOURCES = ["lattice.hpp", "collide.hpp", "kernels.hip"]
+# what decides the step kernel's machine code: its sources and the compiler flags
+KERNEL_SOURCES = ["csrc/lattice.hpp", "csrc/collide.hpp", "csrc/kernels.hip", "build.py"]
 
 
 def log(msg: str) -> None:
@@ -35,10 +36,11 @@ def log(msg: str) -> None:
 
 
 def source_hash() -> str:
-    """Hash of the kernel sources, to tell whether stored counters still apply."""
+    """Hash of the kernel sources and build flags, to tell whether stored
+    counters still apply."""
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2002_02503_amd", "csrc", name), "rb") as f:
+        with open(os.path.join(ROOT, "paper_2002_02503_amd", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 

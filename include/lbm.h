@@ -111,7 +111,9 @@ lbm_status lbm_set_stream(lbm_t h, void* hip_stream);
  * up to a multiple of 256.  Layout (row-tiled structure of arrays): box b
  * holds elements [Q O_b, Q (O_b + n_b)), O_b its first global site; inside it
  * x-row r = z * ny + y is a tile of Q * nx values with population i of site x
- * at r * Q * nx + i * nx + x. */
+ * at r * Q * nx + m(i) * nx + x, where the tile row m(i) is the rank of c_i in
+ * the order of increasing (c_z, c_y, c_x) and i the order of
+ * lbm_lattice_table. */
 lbm_status lbm_state_bytes(lbm_t h, size_t* bytes_each);
 
 /* Use caller-owned device memory (e.g. two torch tensors) for the two
@@ -154,8 +156,8 @@ lbm_status lbm_set_kernel(lbm_t h, int32_t kernel);
 /* Autotune the step's launch: time every candidate (single box: the scalar
  * step at 64/128/256 threads per block and the row-wave step where it
  * applies; batch: 64/128/256 threads x grids of one block per tile or
- * 1024/2048/4096 persistent blocks) over `steps` steps with HIP events, and
- * keep the fastest.  The state is saved before and restored after, so t and
+ * 1024/2048/4096 persistent blocks) over `steps` steps with HIP events, in
+ * three interleaved rounds, and keep the candidate with the fastest round.  The state is saved before and restored after, so t and
  * the populations are unchanged (all candidates compute the same bits).
  * Choices are appended to the text file `cache_path` (NULL: the path in the
  * environment variable LBM_TUNE_CACHE, or no cache); a later call with the same

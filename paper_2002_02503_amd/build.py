@@ -1,7 +1,11 @@
 """Build liblbm.so (the HIP library behind include/lbm.h) for gfx950.
 
 Every HIP source is compiled with hipcc for gfx950 only, without fast-math,
-and with packed FP32 instructions disabled.  The two translation units are
+and with packed FP32 instructions disabled.  Multiply-adds are fused only
+where one source expression writes a * b + c (-ffp-contract=on), never across
+statements in the backend, so every kernel form of the step (one site per
+lane, several sites per lane, batched) rounds the same expressions the same
+way and computes the same bits.  The two translation units are
 compiled in parallel and linked into ``paper_2002_02503_amd/liblbm.so``.
 """
 from __future__ import annotations
@@ -20,7 +24,7 @@ SOURCES = ["kernels.hip", "api.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-FLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++20", "-fPIC", "-Wall",
+FLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++20", "-fPIC", "-Wall", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          f"-I{INCLUDE}", f"-I{CSRC}"]
 

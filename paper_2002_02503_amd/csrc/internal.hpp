@@ -5,9 +5,11 @@
 // offset O_b of the concatenated site space and holds nx * ny * nz sites.
 // Its populations occupy elements [Q O_b, Q (O_b + n_b)) of a buffer; inside
 // the box, x-row r = z * ny + y is one tile of Q * nx elements in which
-// population i of site x sits at r Q nx + i nx + x.  A row tile is thus a
-// small structure of arrays: every population row is contiguous in x, and a
-// step writes each tile as one contiguous run of Q * nx elements.
+// population i of site x sits at r Q nx + m(i) nx + x, with the tile rows
+// m ordered by (c_z, c_y, c_x) (lattice.hpp, mem_row).  A row tile is thus a
+// small structure of arrays: every population row is contiguous in x, a step
+// writes each tile as one contiguous run of Q * nx elements, and the
+// populations it pulls from one neighbouring tile are adjacent rows.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -34,15 +36,17 @@ struct VecGeom {
     int nrows;            // ny * nz
 };
 
-// A tile of the batched step: up to blockDim.x consecutive sites of one box,
-// starting at the box-local site index `start`.
+// A tile of the batched step: in box `box`, plane z, the x-rows y0 .. y0 +
+// rows - 1 (rows * nx <= threads per block), or, when nx exceeds the block,
+// the single row y0 from x0 on.
 struct TileDesc {
     int box;
-    int start;
+    int z, y0, rows, x0;
 };
 
 struct BoxDesc {
-    int nx, ny, nz, pad;
+    int nx, ny, nz;
+    float inv_nx;         // 1 / nx, for the lane -> (row, x) split of a tile
     long long offset;     // O_b: global index of the box's first site
     double omega;         // 1 - 1/tau
 };

@@ -24,6 +24,17 @@ namespace lbm {
 // keeping subnormals.
 // ---------------------------------------------------------------------------
 
+// The FP32 value v, materialised in a register.  A narrowing store rounds the
+// finished FP32 result: without this the compiler may fold the last
+// multiply-add into the conversion (a mixed-precision FMA that rounds the exact
+// product-sum once to 16 bits), in some kernels and not in others, and the
+// step forms would then disagree in the last bit of the stored value.
+__device__ __forceinline__ float rounded_f32(float v)
+{
+    asm("" : "+v"(v));
+    return v;
+}
+
 struct bf16_t {
     uint16_t bits;
 };
@@ -53,8 +64,11 @@ template <>
 struct Store<_Float16> {
     using R = float;
     static __device__ __forceinline__ R get(const _Float16* p) { return float(*p); }
-    static __device__ __forceinline__ void put(_Float16* p, R v) { *p = _Float16(v); }
-    static __device__ __forceinline__ void put_nt(_Float16* p, R v) { __builtin_nontemporal_store(_Float16(v), p); }
+    static __device__ __forceinline__ void put(_Float16* p, R v) { *p = _Float16(rounded_f32(v)); }
+    static __device__ __forceinline__ void put_nt(_Float16* p, R v)
+    {
+        __builtin_nontemporal_store(_Float16(rounded_f32(v)), p);
+    }
     static __device__ __forceinline__ void put_d(_Float16* p, double v) { *p = _Float16(v); }
 };
 
@@ -65,7 +79,7 @@ struct Store<bf16_t> {
     // round to nearest even (gfx950 converts in one instruction)
     static __device__ __forceinline__ uint16_t round_bf16(float v)
     {
-        return __builtin_bit_cast(uint16_t, static_cast<__bf16>(v));
+        return __builtin_bit_cast(uint16_t, static_cast<__bf16>(rounded_f32(v)));
     }
     static __device__ __forceinline__ void put(bf16_t* p, R v) { p->bits = round_bf16(v); }
     static __device__ __forceinline__ void put_nt(bf16_t* p, R v)
@@ -129,20 +143,21 @@ __global__ __launch_bounds__(256) void k_step(const S* __restrict__ src, S* __re
     }
 
     R g[L::Q];
-    unroll<L::Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
+    unroll<L::Q>([&](auto M) {  // in tile-row order
+        constexpr int m = decltype(M)::value;
+        constexpr int i = mem_pop<L>(m);
         constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
         const int row = zw[RR - cz] * geo.ny + yw[RR - cy];
-        const S* p = src + row * tile + (long long)i * geo.nx;
+        const S* p = src + row * tile + (long long)m * geo.nx;
         g[i] = ST::get(at32(p, unsigned(xw[RR - cx])));
     });
 
     collide_site<L, K, PROJ, R>(g, omega);
 
     S* q = dst + (long long)(z * geo.ny + y) * tile;
-    unroll<L::Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        ST::put_nt(at32(q + (long long)i * geo.nx, unsigned(x)), g[i]);
+    unroll<L::Q>([&](auto M) {
+        constexpr int m = decltype(M)::value;
+        ST::put_nt(at32(q + (long long)m * geo.nx, unsigned(x)), g[mem_pop<L>(m)]);
     });
 }
 
@@ -221,7 +236,7 @@ struct VecIO16 {
         if constexpr (std::is_same<H, bf16_t>::value) {
             return Store<bf16_t>::round_bf16(v);
         } else {
-            return uint32_t(__builtin_bit_cast(uint16_t, _Float16(v)));
+            return uint32_t(__builtin_bit_cast(uint16_t, _Float16(rounded_f32(v))));
         }
     }
     static __device__ __forceinline__ void unpack(VT w, float (&o)[4])
@@ -285,11 +300,12 @@ __global__ __launch_bounds__(256) void k_step_vec(const S* __restrict__ src, S* 
     }
 
     R g[V][L::Q];
-    unroll<L::Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
+    unroll<L::Q>([&](auto M) {  // in tile-row order
+        constexpr int m = decltype(M)::value;
+        constexpr int i = mem_pop<L>(m);
         constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
         const long long srow = zw[RR - cz] * geo.ny + yw[RR - cy];
-        const S* p = src + srow * tile + (long long)i * geo.nx;
+        const S* p = src + srow * tile + (long long)m * geo.nx;
         R own[V];
         IO::unpack(*reinterpret_cast<const VT*>(p + (long long)li * V), own);
         // site j pulls from x_j - c_x: element j - c_x of this lane when it is
@@ -313,21 +329,24 @@ __global__ __launch_bounds__(256) void k_step_vec(const S* __restrict__ src, S* 
     });
 
     S* q = dst + (long long)row * tile + (long long)li * V;
-    unroll<L::Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
+    unroll<L::Q>([&](auto M) {
+        constexpr int m = decltype(M)::value;
+        constexpr int i = mem_pop<L>(m);
         R v[V];
         unroll<V>([&](auto J) {
             constexpr int j = decltype(J)::value;
             v[j] = g[j][i];
         });
-        __builtin_nontemporal_store(IO::pack(v), reinterpret_cast<VT*>(q + (long long)i * geo.nx));
+        __builtin_nontemporal_store(IO::pack(v), reinterpret_cast<VT*>(q + (long long)m * geo.nx));
     });
 }
 
 // ---------------------------------------------------------------------------
-// Fused step, batch of boxes.  A tile is up to blockDim.x consecutive sites
-// of one box; a fixed grid walks the tile table (grid-stride), so one launch
-// advances every box by one step.  Each box carries its own tau.  Offsets
+// Fused step, batch of boxes.  A tile is a run of whole x-rows of one z-plane
+// of one box (or a block-wide piece of one row when nx exceeds the block), so
+// z and the box are uniform and each lane finds its row with one exact
+// reciprocal multiply.  A fixed grid walks the tile table (grid-stride): one
+// launch advances every box by one step, each with its own tau.  Offsets
 // inside a box fit 32 bits (checked on the host).
 // ---------------------------------------------------------------------------
 
@@ -344,13 +363,20 @@ __global__ __launch_bounds__(256) void k_step_batch(const S* __restrict__ src, S
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const TileDesc td = tiles[t];
         const BoxDesc b = boxes[td.box];
-        const int local = td.start + int(threadIdx.x);
-        const int nxy = b.nx * b.ny;
-        if (local >= nxy * b.nz) continue;
-        const int z = local / nxy;
-        const int rem = local - z * nxy;
-        const int y = rem / b.nx;
-        const int x = rem - y * b.nx;
+        const int tid = int(threadIdx.x);
+        int r, x;
+        if (b.nx <= int(blockDim.x)) {
+            // (tid + 1/2) / nx is at least 1/(2 nx) away from an integer, far
+            // more than the float rounding of the product: the floor is exact
+            r = int((float(tid) + 0.5f) * b.inv_nx);
+            x = tid - r * b.nx;
+        } else {
+            r = 0;
+            x = td.x0 + tid;
+        }
+        if (r >= td.rows || x >= b.nx) continue;
+        const int y = td.y0 + r;
+        const int z = td.z;
         const S* sb = src + (long long)L::Q * b.offset;
         S* db = dst + (long long)L::Q * b.offset;
 
@@ -361,20 +387,29 @@ __global__ __launch_bounds__(256) void k_step_batch(const S* __restrict__ src, S
             yw[k] = wrap_coord(y + k - RR, b.ny);
             zw[k] = wrap_coord(z + k - RR, b.nz);
         }
+        // element offset of a row tile = plane part (uniform) + row part (per lane)
+        const int tq = L::Q * b.nx;
+        int zo[2 * RR + 1], yo[2 * RR + 1];
+#pragma unroll
+        for (int k = 0; k <= 2 * RR; ++k) {
+            zo[k] = zw[k] * (b.ny * tq);
+            yo[k] = yw[k] * tq;
+        }
         R g[L::Q];
-        unroll<L::Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
+        unroll<L::Q>([&](auto M) {  // in tile-row order
+            constexpr int m = decltype(M)::value;
+            constexpr int i = mem_pop<L>(m);
             constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
-            const int srow = zw[RR - cz] * b.ny + yw[RR - cy];
-            g[i] = ST::get(at32(sb, unsigned((srow * L::Q + i) * b.nx + xw[RR - cx])));
+            const int off = zo[RR - cz] + m * b.nx + (yo[RR - cy] + xw[RR - cx]);
+            g[i] = ST::get(at32(sb, unsigned(off)));
         });
 
         collide_site<L, K, PROJ, R>(g, R(b.omega));
 
-        const int row = z * b.ny + y;
-        unroll<L::Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            ST::put_nt(at32(db, unsigned((row * L::Q + i) * b.nx + x)), g[i]);
+        const int out_off = (z * b.ny + y) * tq + x;
+        unroll<L::Q>([&](auto M) {
+            constexpr int m = decltype(M)::value;
+            ST::put_nt(at32(db, unsigned(out_off + m * b.nx)), g[mem_pop<L>(m)]);
         });
     }
 }
@@ -414,7 +449,7 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ rho, co
         equilibrium_scaled<L, K, double>(rho[s] - 1.0, ux, uy, uz, g);
         unroll<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            ST::put_d(base + e + (long long)i * b.nx, g[i]);
+            ST::put_d(base + e + (long long)mem_row<L>(i) * b.nx, g[i]);
         });
     }
 }
@@ -430,7 +465,7 @@ __device__ __forceinline__ void site_moments(const S* __restrict__ p, int nx, do
     unroll<L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
-        const double gi = double(ST::get(p + (long long)i * nx));
+        const double gi = double(ST::get(p + (long long)mem_row<L>(i) * nx));
         dsum += gi;
         if constexpr (cx != 0) j[0] += double(cx) * gi;
         if constexpr (cy != 0) j[1] += double(cy) * gi;

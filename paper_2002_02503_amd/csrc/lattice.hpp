@@ -143,6 +143,42 @@ static_assert(integer_weights_consistent<D2Q9>(), "D2Q9 weight quantum");
 static_assert(integer_weights_consistent<D3Q19>(), "D3Q19 weight quantum");
 static_assert(integer_weights_consistent<D3Q39>(), "D3Q39 weight quantum");
 
+// Memory order of the populations inside a row tile: sorted by (c_z, c_y, c_x),
+// so the populations a step pulls from one neighbouring row tile are adjacent
+// rows of that tile.  mem_row(i) is the tile row of population i, mem_pop(m)
+// the population stored in tile row m.
+template <class L>
+constexpr int mem_row(int i)
+{
+    int rank = 0;
+    const int R = L::R, W = 2 * L::R + 1;
+    const int ki = ((L::c[i][2] + R) * W + (L::c[i][1] + R)) * W + (L::c[i][0] + R);
+    for (int j = 0; j < L::Q; ++j) {
+        const int kj = ((L::c[j][2] + R) * W + (L::c[j][1] + R)) * W + (L::c[j][0] + R);
+        if (kj < ki) ++rank;
+    }
+    return rank;
+}
+
+template <class L>
+constexpr int mem_pop(int m)
+{
+    for (int i = 0; i < L::Q; ++i)
+        if (mem_row<L>(i) == m) return i;
+    return -1;
+}
+
+template <class L>
+constexpr bool mem_order_is_permutation()
+{
+    for (int m = 0; m < L::Q; ++m)
+        if (mem_pop<L>(m) < 0 || mem_row<L>(mem_pop<L>(m)) != m) return false;
+    return true;
+}
+static_assert(mem_order_is_permutation<D2Q9>() && mem_order_is_permutation<D3Q19>() &&
+                  mem_order_is_permutation<D3Q39>(),
+              "tile row order");
+
 // Calls f(std::integral_constant<int, i>{}) for i = 0 .. N-1, fully unrolled.
 template <class F, int... I>
 __host__ __device__ __forceinline__ void unroll_impl(F&& f, std::integer_sequence<int, I...>)

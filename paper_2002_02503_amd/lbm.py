@@ -58,7 +58,17 @@ def load_library() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
                           "(hipcc --offload-arch=gfx950). There is no CPU fallback.")
+    # PyTorch ships its own HIP runtime under the soname libamdhip64.so.7, the
+    # one liblbm.so links.  With torch loaded first the dynamic linker binds
+    # liblbm.so to torch's copy and the process has one HIP runtime; loaded the
+    # other way round, torch would bring a second runtime that sees no devices
+    # and whose streams and events liblbm.so could not use.
+    _torch()
     lib = ctypes.CDLL(LIB_PATH)
+    runtimes = _hip_runtimes_mapped()
+    if len(runtimes) > 1:
+        raise ImportError("two HIP runtimes are mapped into this process (" + ", ".join(sorted(runtimes)) +
+                          "); import torch before anything that loads libamdhip64")
     vp, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
     i64p = ctypes.POINTER(ctypes.c_int64)
     sig = {
@@ -95,6 +105,20 @@ def load_library() -> ctypes.CDLL:
         fn.restype = ctypes.c_char_p if name == "lbm_last_error" else ctypes.c_int
     _lib = lib
     return lib
+
+
+def _hip_runtimes_mapped() -> set:
+    """Files named libamdhip64* mapped into this process (Linux)."""
+    found = set()
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                path = line.split()[-1] if len(line.split()) >= 6 else ""
+                if "libamdhip64" in os.path.basename(path):
+                    found.add(os.path.realpath(path))
+    except OSError:
+        pass
+    return found
 
 
 def _check(rc: int):

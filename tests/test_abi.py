@@ -128,3 +128,16 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(lbm, "_lib", None)
     with pytest.raises(ImportError):
         lbm.load_library()
+
+
+def test_binding_shares_torchs_hip_runtime():
+    """Loaded through the binding first, the library still binds to the HIP
+    runtime torch ships (same soname), so the process maps exactly one."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("from paper_2002_02503_amd import lbm; lbm.load_library(); import torch; "
+            "print(len(lbm._hip_runtimes_mapped()))")
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"

@@ -207,8 +207,11 @@ def test_batched_256_boxes_fp32():
     dm = np.abs(tot1[:, 0] - mass) / mass
     dp = np.abs(tot1[:, 1:] - tot0[:, 1:]).max(axis=1) / mass
     print(f"batched: worst mass drift {dm.max():.2e}, momentum drift {dp.max():.2e}", flush=True)
-    # single-precision round-off over 1000 steps (FP32 epsilon 6e-8)
-    assert np.all(dm < 2e-7) and np.all(dp < 2e-7)
+    # Single-precision round-off only: each step rounds every stored value to
+    # FP32 (epsilon 6e-8); even if all of it added up, 1000 steps at |u| <= 0.2
+    # would drift by steps * epsilon * 0.2 = 1.2e-5.  A collision that broke
+    # conservation would drift by O(|u|^2) = 1e-3 or more.
+    assert np.all(dm < 1e-6) and np.all(dp < 1e-6)
     worst = 0.0
     for k in range(0, len(boxes), 16):
         nx, ny, nz = boxes[k]["dims"]
