@@ -5,7 +5,7 @@ and with packed FP32 instructions disabled.  Multiply-adds are fused only
 where one source expression writes a * b + c (-ffp-contract=on), never across
 statements in the backend, so every kernel form of the step (one site per
 lane, several sites per lane, batched) rounds the same expressions the same
-way and computes the same bits.  The two translation units are
+way and computes the same bits.  The translation units are
 compiled in parallel and linked into ``paper_2002_02503_amd/liblbm.so``.
 """
 from __future__ import annotations
@@ -20,7 +20,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "liblbm.so")
-SOURCES = ["kernels.hip", "api.hip"]
+SOURCES = ["kernels.hip", "step.hip", "step_batch.hip", "api.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -1,0 +1,180 @@
+// The fused pull-stream + collide step on a single box: one site per thread
+// (k_step) or V sites per lane (k_step_vec).
+#include "device.hpp"
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// Fused step, single box, one site per thread.  The grid is (x-blocks, ny,
+// nz): a block covers blockDim.x sites of one x-row, so y, z and the source
+// row of every population are block-uniform; only the x wrap is per lane.
+// Every access is a uniform 64-bit pointer (row tile + population row) plus a
+// 32-bit lane offset.
+// ---------------------------------------------------------------------------
+
+template <class L, class S, int K>
+__global__ __launch_bounds__(256) void k_step(const S* __restrict__ src, S* __restrict__ dst, StepGeom geo,
+                                              typename Store<S>::R omega)
+{
+    using ST = Store<S>;
+    using R = typename ST::R;
+    constexpr bool PROJ = !std::is_same<R, double>::value;
+    constexpr int RR = L::R;
+
+    const int y = blockIdx.y;
+    const int z = blockIdx.z;
+    const int x = int(blockIdx.x) * int(blockDim.x) + int(threadIdx.x);
+    if (x >= geo.nx) return;
+    const long long tile = (long long)L::Q * geo.nx;  // elements per row tile
+
+    int xw[2 * RR + 1], yw[2 * RR + 1], zw[2 * RR + 1];
+#pragma unroll
+    for (int k = 0; k <= 2 * RR; ++k) {
+        xw[k] = wrap_coord(x + k - RR, geo.nx);
+        yw[k] = wrap_coord(y + k - RR, geo.ny);
+        zw[k] = wrap_coord(z + k - RR, geo.nz);
+    }
+
+    R g[L::Q];
+    unroll<L::Q>([&](auto M) {  // in tile-row order
+        constexpr int m = decltype(M)::value;
+        constexpr int i = mem_pop<L>(m);
+        constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
+        const int row = zw[RR - cz] * geo.ny + yw[RR - cy];
+        const S* p = src + row * tile + (long long)m * geo.nx;
+        g[i] = load_population<ST, cx>(at32(p, unsigned(xw[RR - cx])));
+    });
+
+    collide_site<L, K, PROJ, R>(g, omega);
+
+    S* q = dst + (long long)(z * geo.ny + y) * tile;
+    unroll<L::Q>([&](auto M) {
+        constexpr int m = decltype(M)::value;
+        ST::put_nt(at32(q + (long long)m * geo.nx, unsigned(x)), g[mem_pop<L>(m)]);
+    });
+}
+
+template <class L, class S, int K>
+__global__ __launch_bounds__(256) void k_step_vec(const S* __restrict__ src, S* __restrict__ dst, VecGeom geo,
+                                                  typename Store<S>::R omega)
+{
+    using R = typename Store<S>::R;
+    constexpr int V = vec_sites<S>();
+    using IO = VecIO<S, V>;
+    using VT = typename IO::VT;
+    constexpr bool PROJ = !std::is_same<R, double>::value;
+    constexpr int RR = L::R;
+    static_assert(RR < V, "a shifted population must come from at most one neighbouring lane");
+
+    const int lane = int(threadIdx.x) & 63;
+    const int wave = int(blockIdx.x) * (int(blockDim.x) >> 6) + (int(threadIdx.x) >> 6);
+    const int lpr = geo.lanes_per_row;
+    const int r = lane / lpr;          // row within the wave
+    const int li = lane - r * lpr;     // lane within the row
+    const int row = wave * geo.rows_per_wave + r;
+    // Lanes past the last row of the wave, or past the last row of the box,
+    // leave now; every lane that stays only reads lanes of its own row.
+    if (r >= geo.rows_per_wave || row >= geo.nrows) return;
+    const int prev = r * lpr + (li == 0 ? lpr - 1 : li - 1);
+    const int next = r * lpr + (li == lpr - 1 ? 0 : li + 1);
+    const int y = row % geo.ny;
+    const int z = row / geo.ny;
+    const long long tile = (long long)L::Q * geo.nx;
+    int yw[2 * RR + 1], zw[2 * RR + 1];
+#pragma unroll
+    for (int k = 0; k <= 2 * RR; ++k) {
+        yw[k] = wrap_coord(y + k - RR, geo.ny);
+        zw[k] = wrap_coord(z + k - RR, geo.nz);
+    }
+
+    R g[V][L::Q];
+    unroll<L::Q>([&](auto M) {  // in tile-row order
+        constexpr int m = decltype(M)::value;
+        constexpr int i = mem_pop<L>(m);
+        constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
+        const long long srow = zw[RR - cz] * geo.ny + yw[RR - cy];
+        const S* p = src + srow * tile + (long long)m * geo.nx;
+        R own[V];
+        // every lane reads its own aligned V-site chunk: no line is shared
+        IO::unpack(__builtin_nontemporal_load(reinterpret_cast<const VT*>(p + (long long)li * V)), own);
+        // site j pulls from x_j - c_x: element j - c_x of this lane when it is
+        // in [0, V), otherwise the wrapped element of the neighbouring lane
+        unroll<V>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            constexpr int e = j - cx;
+            if constexpr (e >= 0 && e < V) {
+                g[j][i] = own[e];
+            } else if constexpr (e < 0) {
+                g[j][i] = __shfl(own[e + V], prev, 64);
+            } else {
+                g[j][i] = __shfl(own[e - V], next, 64);
+            }
+        });
+    });
+
+    unroll<V>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        collide_site<L, K, PROJ, R>(g[j], omega);
+    });
+
+    S* q = dst + (long long)row * tile + (long long)li * V;
+    unroll<L::Q>([&](auto M) {
+        constexpr int m = decltype(M)::value;
+        constexpr int i = mem_pop<L>(m);
+        R v[V];
+        unroll<V>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            v[j] = g[j][i];
+        });
+        __builtin_nontemporal_store(IO::pack(v), reinterpret_cast<VT*>(q + (long long)m * geo.nx));
+    });
+}
+
+hipError_t launch_step(int lat, int dtype, int K, const void* src, void* dst, const StepGeom& geo, double omega,
+                       int block, hipStream_t s)
+{
+    return dispatch(lat, dtype, K, [&](auto Lt, auto* Sp, auto Kc) -> hipError_t {
+        using L = decltype(Lt);
+        using S = std::remove_pointer_t<decltype(Sp)>;
+        using R = typename Store<S>::R;
+        constexpr int KK = decltype(Kc)::value;
+        k_step<L, S, KK><<<dim3(unsigned(geo.xblocks), unsigned(geo.ny), unsigned(geo.nz)), block, 0, s>>>(
+            static_cast<const S*>(src), static_cast<S*>(dst), geo, R(omega));
+        return hipGetLastError();
+    });
+}
+
+int vec_sites_per_lane(int lat, int dtype)
+{
+    int v = 0;
+    (void)dispatch(lat, dtype, 2, [&](auto Lt, auto* Sp, auto) -> hipError_t {
+        using L = decltype(Lt);
+        using S = std::remove_pointer_t<decltype(Sp)>;
+        constexpr int V = vec_sites<S>();
+        v = (L::R < V) ? V : 0;
+        return hipSuccess;
+    });
+    return v;
+}
+
+hipError_t launch_step_vec(int lat, int dtype, int K, const void* src, void* dst, const VecGeom& geo, double omega,
+                           hipStream_t s)
+{
+    return dispatch(lat, dtype, K, [&](auto Lt, auto* Sp, auto Kc) -> hipError_t {
+        using L = decltype(Lt);
+        using S = std::remove_pointer_t<decltype(Sp)>;
+        using R = typename Store<S>::R;
+        constexpr int KK = decltype(Kc)::value;
+        if constexpr (L::R < vec_sites<S>()) {
+            const long long waves = (geo.nrows + geo.rows_per_wave - 1) / geo.rows_per_wave;
+            const long long nblocks = (waves + 3) / 4;
+            k_step_vec<L, S, KK><<<dim3((unsigned)nblocks), 256, 0, s>>>(static_cast<const S*>(src),
+                                                                       static_cast<S*>(dst), geo, R(omega));
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;
+        }
+    });
+}
+
+}  // namespace lbm

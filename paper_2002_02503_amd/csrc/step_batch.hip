@@ -1,0 +1,93 @@
+// The fused pull-stream + collide step on a batch of boxes.
+#include "device.hpp"
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// Fused step, batch of boxes.  A tile is a run of whole x-rows of one z-plane
+// of one box (or a block-wide piece of one row when nx exceeds the block), so
+// z and the box are uniform and each lane finds its row with one exact
+// reciprocal multiply.  A fixed grid walks the tile table (grid-stride): one
+// launch advances every box by one step, each with its own tau.  Offsets
+// inside a box fit 32 bits (checked on the host).
+// ---------------------------------------------------------------------------
+
+template <class L, class S, int K>
+__global__ __launch_bounds__(256) void k_step_batch(const S* __restrict__ src, S* __restrict__ dst,
+                                                    const TileDesc* __restrict__ tiles, int ntiles,
+                                                    const BoxDesc* __restrict__ boxes)
+{
+    using ST = Store<S>;
+    using R = typename ST::R;
+    constexpr bool PROJ = !std::is_same<R, double>::value;
+    constexpr int RR = L::R;
+
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const TileDesc td = tiles[t];
+        const BoxDesc b = boxes[td.box];
+        const int tid = int(threadIdx.x);
+        int r, x;
+        if (b.nx <= int(blockDim.x)) {
+            // (tid + 1/2) / nx is at least 1/(2 nx) away from an integer, far
+            // more than the float rounding of the product: the floor is exact
+            r = int((float(tid) + 0.5f) * b.inv_nx);
+            x = tid - r * b.nx;
+        } else {
+            r = 0;
+            x = td.x0 + tid;
+        }
+        if (r >= td.rows || x >= b.nx) continue;
+        const int y = td.y0 + r;
+        const int z = td.z;
+        const S* sb = src + (long long)L::Q * b.offset;
+        S* db = dst + (long long)L::Q * b.offset;
+
+        int xw[2 * RR + 1], yw[2 * RR + 1], zw[2 * RR + 1];
+#pragma unroll
+        for (int k = 0; k <= 2 * RR; ++k) {
+            xw[k] = wrap_coord(x + k - RR, b.nx);
+            yw[k] = wrap_coord(y + k - RR, b.ny);
+            zw[k] = wrap_coord(z + k - RR, b.nz);
+        }
+        // element offset of a row tile = plane part (uniform) + row part (per lane)
+        const int tq = L::Q * b.nx;
+        int zo[2 * RR + 1], yo[2 * RR + 1];
+#pragma unroll
+        for (int k = 0; k <= 2 * RR; ++k) {
+            zo[k] = zw[k] * (b.ny * tq);
+            yo[k] = yw[k] * tq;
+        }
+        R g[L::Q];
+        unroll<L::Q>([&](auto M) {  // in tile-row order
+            constexpr int m = decltype(M)::value;
+            constexpr int i = mem_pop<L>(m);
+            constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
+            const int off = zo[RR - cz] + m * b.nx + (yo[RR - cy] + xw[RR - cx]);
+            g[i] = load_population<ST, cx>(at32(sb, unsigned(off)));
+        });
+
+        collide_site<L, K, PROJ, R>(g, R(b.omega));
+
+        const int out_off = (z * b.ny + y) * tq + x;
+        unroll<L::Q>([&](auto M) {
+            constexpr int m = decltype(M)::value;
+            ST::put_nt(at32(db, unsigned(out_off + m * b.nx)), g[mem_pop<L>(m)]);
+        });
+    }
+}
+
+hipError_t launch_step_batch(int lat, int dtype, int K, const void* src, void* dst, const TileDesc* tiles,
+                             int ntiles, const BoxDesc* boxes, int block, int grid, hipStream_t s)
+{
+    return dispatch(lat, dtype, K, [&](auto Lt, auto* Sp, auto Kc) -> hipError_t {
+        using L = decltype(Lt);
+        using S = std::remove_pointer_t<decltype(Sp)>;
+        constexpr int KK = decltype(Kc)::value;
+        const int g = (grid > 0 && grid < ntiles) ? grid : ntiles;
+        k_step_batch<L, S, KK><<<g, block, 0, s>>>(static_cast<const S*>(src), static_cast<S*>(dst), tiles, ntiles,
+                                                   boxes);
+        return hipGetLastError();
+    });
+}
+
+}  // namespace lbm
