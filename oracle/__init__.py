@@ -24,12 +24,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.c")
 _LIB = os.path.join(_HERE, "liblbm_oracle.so")
 
-LATTICES = {"D2Q9": 0, "D3Q19": 1, "D3Q39": 2}
+LATTICES = {"D2Q9": 0, "D3Q19": 1, "D3Q39": 2, "D3Q15": 3}
 KINDS = {"filtered": 0, "bgk": 1, "none": 2}
 MODES = {"literal": 0, "closed": 1}
 
 # Default Hermite truncation order per lattice (reading R1 in the C header).
-DEFAULT_K = {"D2Q9": 3, "D3Q19": 3, "D3Q39": 4}
+DEFAULT_K = {"D2Q9": 3, "D3Q15": 3, "D3Q19": 3, "D3Q39": 4}
 
 _lock = threading.Lock()
 _lib = None
@@ -62,12 +62,13 @@ def _load():
         lib.oracle_hermite.argtypes = [ctypes.c_int, ctypes.c_int, dp]
         lib.oracle_feq.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp]
         lib.oracle_fneq.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, dp]
+        lib.oracle_fq.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp]
         lib.oracle_collide.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                       ctypes.c_int, ctypes.c_double, dp, dp]
+                                       ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp]
         lib.oracle_sim_create.restype = ctypes.c_void_p
         lib.oracle_sim_create.argtypes = [ctypes.c_int, ctypes.c_long, ctypes.c_long, ctypes.c_long,
                                           ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                          ctypes.c_int]
+                                          ctypes.c_int, ctypes.c_double]
         lib.oracle_sim_destroy.argtypes = [ctypes.c_void_p]
         lib.oracle_sim_init.argtypes = [ctypes.c_void_p, dp, dp]
         lib.oracle_sim_step.argtypes = [ctypes.c_void_p, ctypes.c_long]
@@ -148,15 +149,29 @@ def fneq(name: str, K: int, u, Pi, mode: str = "literal") -> np.ndarray:
     return out
 
 
+def fq(name: str, K: int, u, Qt) -> np.ndarray:
+    """Energy-flux part of eq. pq in Hermite form, truncated at order K (reading
+    R4 of the C file): (w_i / 6 T0^{3/2}) sum_{n=3}^{K} H^(n)(xi_i) (V^[n-3] Qt) / (n-3)!.
+    Qt is a D x D x D (or 3 x 3 x 3) tensor."""
+    Q = lattice(name)["Q"]
+    out = np.zeros(Q)
+    Qt = np.asarray(Qt, dtype=np.float64)
+    q3 = np.zeros((3, 3, 3))
+    q3[: Qt.shape[0], : Qt.shape[1], : Qt.shape[2]] = Qt
+    _check(_load().oracle_fq(LATTICES[name], K, _dp(_vec3(u)), _dp(np.ascontiguousarray(q3)), _dp(out)), "fq")
+    return out
+
+
 def collide(name: str, f, tau: float, K: int | None = None, Keq: int | None = None,
-            kind: str = "filtered", mode: str = "literal") -> np.ndarray:
-    """One collision at one site (eq. post-1 with eq. hermite-coll; eq. BGK)."""
+            kind: str = "filtered", mode: str = "literal", theta: float = 0.0) -> np.ndarray:
+    """One collision at one site (eq. post-1 with eq. hermite-coll, plus theta
+    times the energy-flux part of eq. pq; or eq. BGK)."""
     K = DEFAULT_K[name] if K is None else K
     Keq = K if Keq is None else Keq
     f = np.ascontiguousarray(f, dtype=np.float64)
     out = np.zeros_like(f)
     _check(_load().oracle_collide(LATTICES[name], KINDS[kind], MODES[mode], Keq, K, float(tau),
-                                  _dp(f), _dp(out)), "collide")
+                                  float(theta), _dp(f), _dp(out)), "collide")
     return out
 
 
@@ -170,13 +185,14 @@ def get_threads() -> int:
 
 class Sim:
     """Periodic box evolved by the lattice Boltzmann equation (eq. lbe-reg).
+    ``theta`` weights the energy-flux part of eq. pq (filtered kind only).
 
     ``dims`` is (nx, ny, nz); D2Q9 needs nz == 1.  Fields use the layout
     rho[z, y, x] and u[a, z, y, x].  The stored state is post-collision
     (reading R3)."""
 
     def __init__(self, name: str, dims, tau: float, K: int | None = None, Keq: int | None = None,
-                 kind: str = "filtered", mode: str = "literal"):
+                 kind: str = "filtered", mode: str = "literal", theta: float = 0.0):
         self.lib = _load()
         self.name = name
         self.lat = lattice(name)
@@ -185,8 +201,9 @@ class Sim:
         self.K = DEFAULT_K[name] if K is None else K
         self.Keq = self.K if Keq is None else Keq
         self.tau = float(tau)
+        self.theta = float(theta)
         self.h = self.lib.oracle_sim_create(LATTICES[name], nx, ny, nz, float(tau), self.Keq, self.K,
-                                            KINDS[kind], MODES[mode])
+                                            KINDS[kind], MODES[mode], self.theta)
         if not self.h:
             raise ValueError("oracle_sim_create rejected its arguments")
         self.nsites = nx * ny * nz

@@ -26,10 +26,18 @@
  *   R3  Streaming is written in pull form: f_i(x, t+1) = f'_i(x - c_i, t),
  *       which is eq. lbe read from the arrival site.  Every axis is periodic.
  *       The stored state is the post-collision population.
- *   R4  theta = 0: the energy-flux term of eq. filter2 / eq. pq is absent.
+ *   R4  The energy-flux term of eq. pq has weight theta (default 0).  Its
+ *       compact form eq. filter-Q is read with f^eq / rho in place of f^eq,
+ *       as in eq. filter-coll, so that at u = 0 it reduces to the theta term
+ *       of eq. filter2.  Its Hermite expansion follows from the generating
+ *       function exp(xi.t - t.t/2) of the H^(n) exactly as eq. hermite-coll
+ *       follows from eq. filter-coll (three t-derivatives instead of two):
+ *           fhat^q_i = (w_i / 6 T0^{3/2}) sum_{n>=3} H^(n)(xi_i) (V^[n-3] Qt) / (n-3)!
+ *       and it is truncated at the same order K.  Qt is the relative energy
+ *       flux eq. Q_def, computed literally with c' = c - u.
  *   R5  Lattice weights and T0 are not printed in the paper.  D2Q9 and
- *       D3Q19 use T0 = 1/3 (stated in the section on isotropy) with the
- *       standard shell weights; D3Q39 uses T0 = 2/3 and the six shell
+ *       D3Q15 and D3Q19 use T0 = 1/3 (stated in the section on isotropy) with
+ *       the standard shell weights; D3Q39 uses T0 = 2/3 and the six shell
  *       weights that satisfy the isotropy condition eq. iso through 6th
  *       order (the test suite re-derives them from eq. iso).
  *
@@ -50,7 +58,7 @@
 #define OR_QMAX 39
 #define OR_NMAX 10 /* highest Hermite order the tensor tables are built to */
 
-enum { OR_D2Q9 = 0, OR_D3Q19 = 1, OR_D3Q39 = 2, OR_NLAT = 3 };
+enum { OR_D2Q9 = 0, OR_D3Q19 = 1, OR_D3Q39 = 2, OR_D3Q15 = 3, OR_NLAT = 4 };
 enum { OR_KIND_FILTERED = 0, OR_KIND_BGK = 1, OR_KIND_NONE = 2 };
 enum { OR_MODE_LITERAL = 0, OR_MODE_CLOSED = 1 };
 enum { OR_OK = 0, OR_EINVAL = -1, OR_ENOMEM = -2 };
@@ -79,6 +87,8 @@ static int lattice_make(int lat, lattice_t* L)
         {{0, 0, 0}, 4.0 / 9.0}, {{1, 0, 0}, 1.0 / 9.0}, {{1, 1, 0}, 1.0 / 36.0}};
     static const shell_t d3q19[] = {
         {{0, 0, 0}, 1.0 / 3.0}, {{1, 0, 0}, 1.0 / 18.0}, {{1, 1, 0}, 1.0 / 36.0}};
+    static const shell_t d3q15[] = {
+        {{0, 0, 0}, 2.0 / 9.0}, {{1, 0, 0}, 1.0 / 9.0}, {{1, 1, 1}, 1.0 / 72.0}};
     static const shell_t d3q39[] = {
         {{0, 0, 0}, 1.0 / 12.0},  {{1, 0, 0}, 1.0 / 12.0},  {{1, 1, 1}, 1.0 / 27.0},
         {{2, 0, 0}, 2.0 / 135.0}, {{2, 2, 0}, 1.0 / 432.0}, {{3, 0, 0}, 1.0 / 1620.0}};
@@ -89,6 +99,7 @@ static int lattice_make(int lat, lattice_t* L)
     case OR_D2Q9:  sh = d2q9;  nsh = 3; L->D = 2; L->T0 = 1.0 / 3.0; L->two_n = 4; break;
     case OR_D3Q19: sh = d3q19; nsh = 3; L->D = 3; L->T0 = 1.0 / 3.0; L->two_n = 4; break;
     case OR_D3Q39: sh = d3q39; nsh = 6; L->D = 3; L->T0 = 2.0 / 3.0; L->two_n = 6; break;
+    case OR_D3Q15: sh = d3q15; nsh = 3; L->D = 3; L->T0 = 1.0 / 3.0; L->two_n = 4; break;
     default: return OR_EINVAL;
     }
     int zr = (L->D == 3) ? 3 : 0;
@@ -278,6 +289,56 @@ static void fneq_literal(const lattice_t* L, const hermite_t* H, int K, const do
     for (int i = 0; i < Q; ++i) fneq[i] *= L->w[i] / (2.0 * L->T0);
 }
 
+/* Energy-flux part of eq. pq (reading R4), truncated at order K:
+ *   fhat^q_i = (w_i / 6 T0^{3/2}) sum_{n=3}^{K} H^(n)(xi_i) (V^[n-3] Qt) / (n-3)!
+ * where the last three indices of H^(n) contract with Qt (3x3x3, row-major,
+ * only the leading D x D x D block is read).  Empty for K < 3. */
+static void fq_literal(const lattice_t* L, const hermite_t* H, int K, const double* u,
+                       const double* Qt, double* fq, double* ws)
+{
+    const int D = L->D, Q = L->Q;
+    double V[3];
+    for (int a = 0; a < D; ++a) V[a] = u[a] / sqrt(L->T0);
+    for (int i = 0; i < Q; ++i) fq[i] = 0.0;
+    double mfact = 1.0; /* (n-3)! */
+    for (int n = 3; n <= K; ++n) {
+        if (n > 3) mfact *= (n - 3);
+        const long szv = ipow(D, n - 3), sz = ipow(D, n);
+        double* Vn = ws;
+        double* T = ws + szv;
+        outer_power(V, D, n - 3, Vn);
+        for (long idx = 0; idx < szv; ++idx)
+            for (int a = 0; a < D; ++a)
+                for (int b = 0; b < D; ++b)
+                    for (int g = 0; g < D; ++g)
+                        T[((idx * D + a) * D + b) * D + g] = Vn[idx] * Qt[(a * 3 + b) * 3 + g];
+        for (int i = 0; i < Q; ++i) {
+            const double* Hn = H->H[n] + i * sz;
+            double acc = 0.0;
+            for (long idx = 0; idx < sz; ++idx) acc += Hn[idx] * T[idx];
+            fq[i] += acc / mfact;
+        }
+    }
+    for (int i = 0; i < Q; ++i) fq[i] *= L->w[i] / (6.0 * L->T0 * sqrt(L->T0));
+}
+
+/* Relative non-equilibrium energy flux eq. Q_def, literally:
+ *   Qt = sum_i c'_i c'_i c'_i (f_i - f^eq_i),  c'_i = c_i - u. */
+static void qtilde_literal(const lattice_t* L, const double* f, const double* feq, const double* u,
+                           double* Qt)
+{
+    const int D = L->D;
+    for (int k = 0; k < 27; ++k) Qt[k] = 0.0;
+    for (int i = 0; i < L->Q; ++i) {
+        const double d = f[i] - feq[i];
+        double cp[3] = {0.0, 0.0, 0.0};
+        for (int a = 0; a < D; ++a) cp[a] = L->c[i][a] - u[a];
+        for (int a = 0; a < D; ++a)
+            for (int b = 0; b < D; ++b)
+                for (int g = 0; g < D; ++g) Qt[(a * 3 + b) * 3 + g] += cp[a] * cp[b] * cp[g] * d;
+    }
+}
+
 /* Scalar form of eq. hermite: H^(n)(xi) . V^[n] equals the probabilists'
  * Hermite polynomial He_n(a; v) with a = xi . V, v = V . V, generated by
  * He_{n+1} = a He_n - n v He_{n-1}.  Used by the closed-form mode. */
@@ -359,13 +420,14 @@ static void moments(const lattice_t* L, const double* f, double* rho, double* u)
 
 typedef struct {
     int kind, mode, Keq, Kneq;
-    double tau;
+    double tau, theta;
 } collide_cfg;
 
 /* One collision at one site.
  *   filtered: eq. post-1 with the truncated eq. hermite-coll,
  *             f' = f^eq + (1 - 1/tau) fhat^neq, with Pi^neq = sum c c (f - f^eq)
- *             (eq. coeff-2, equal to eq. Pi_def).
+ *             (eq. coeff-2, equal to eq. Pi_def); with theta != 0 the
+ *             energy-flux part of eq. pq is added: fhat^neq + theta fhat^q.
  *   bgk:      eq. BGK, f' = f - (f - f^eq)/tau.
  *   none:     f' = f (streaming only; used to pin the streaming half).      */
 static int collide(const lattice_t* L, const hermite_t* H, const collide_cfg* cfg,
@@ -396,6 +458,12 @@ static int collide(const lattice_t* L, const hermite_t* H, const collide_cfg* cf
     } else {
         int rc = fneq_closed(L, cfg->Kneq, u, Pi, fneq);
         if (rc != OR_OK) return rc;
+    }
+    if (cfg->theta != 0.0) {
+        double Qt[27], fq[OR_QMAX];
+        qtilde_literal(L, f, feq, u, Qt);
+        fq_literal(L, H, cfg->Kneq, u, Qt, fq, ws);
+        for (int i = 0; i < Q; ++i) fneq[i] += cfg->theta * fq[i];
     }
     const double om = 1.0 - 1.0 / cfg->tau;
     for (int i = 0; i < Q; ++i) fout[i] = feq[i] + om * fneq[i];
@@ -469,16 +537,31 @@ int oracle_fneq(int lat, int K, int mode, const double* u, const double* Pi, dou
     return OR_OK;
 }
 
-int oracle_collide(int lat, int kind, int mode, int Keq, int Kneq, double tau,
+/* Qt: 3x3x3 row-major (only the leading D x D x D block is read). */
+int oracle_fq(int lat, int K, const double* u, const double* Qt, double* out)
+{
+    const lattice_t* L;
+    const hermite_t* H;
+    if (K < 3) return OR_EINVAL;
+    int rc = tables_get(lat, K, &L, &H);
+    if (rc != OR_OK) return rc;
+    double* ws = (double*)malloc(sizeof(double) * scratch_len(L, K));
+    if (!ws) return OR_ENOMEM;
+    fq_literal(L, H, K, u, Qt, out, ws);
+    free(ws);
+    return OR_OK;
+}
+
+int oracle_collide(int lat, int kind, int mode, int Keq, int Kneq, double tau, double theta,
                    const double* f, double* out)
 {
     const lattice_t* L;
     const hermite_t* H;
-    if (Keq < 0 || Kneq < 2 || !(tau > 0.0)) return OR_EINVAL;
+    if (Keq < 0 || Kneq < 2 || !(tau > 0.0) || !isfinite(theta)) return OR_EINVAL;
     int kmax = Keq > Kneq ? Keq : Kneq;
     int rc = tables_get(lat, kmax, &L, &H);
     if (rc != OR_OK) return rc;
-    collide_cfg cfg = {kind, mode, Keq, Kneq, tau};
+    collide_cfg cfg = {kind, mode, Keq, Kneq, tau, theta};
     double* ws = (double*)malloc(sizeof(double) * scratch_len(L, kmax));
     if (!ws) return OR_ENOMEM;
     rc = collide(L, H, &cfg, f, out, ws);
@@ -505,9 +588,10 @@ typedef struct {
 static long wrap(long v, long n) { return ((v % n) + n) % n; }
 
 oracle_sim* oracle_sim_create(int lat, long nx, long ny, long nz, double tau,
-                              int Keq, int Kneq, int kind, int mode)
+                              int Keq, int Kneq, int kind, int mode, double theta)
 {
     if (nx < 1 || ny < 1 || nz < 1 || !(tau > 0.0) || Keq < 0 || Kneq < 2) return NULL;
+    if (!isfinite(theta)) return NULL;
     if (kind < OR_KIND_FILTERED || kind > OR_KIND_NONE) return NULL;
     if (mode == OR_MODE_CLOSED && kind == OR_KIND_FILTERED && (Kneq < 2 || Kneq > 4)) return NULL;
     const lattice_t* L;
@@ -524,6 +608,7 @@ oracle_sim* oracle_sim_create(int lat, long nx, long ny, long nz, double tau,
     s->cfg.Keq = Keq;
     s->cfg.Kneq = Kneq;
     s->cfg.tau = tau;
+    s->cfg.theta = theta;
     s->nx = nx; s->ny = ny; s->nz = nz;
     s->nsites = nx * ny * nz;
     s->f = (double*)calloc((size_t)s->nsites * L->Q, sizeof(double));

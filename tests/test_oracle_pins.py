@@ -16,7 +16,7 @@ from numpy.polynomial import hermite_e
 from lbm_analysis import (hermite_explicit, kronecker_delta_tensor, moment_tensor,
                           sym_perm_delta)
 
-LATS = ["D2Q9", "D3Q19", "D3Q39"]
+LATS = ["D2Q9", "D3Q15", "D3Q19", "D3Q39"]
 RNG = np.random.default_rng(7)
 
 
@@ -37,8 +37,8 @@ def _rand_pi(D, scale=1e-3):
 def test_isotropy_holds_to_2N(oracle_mod, name):
     L = oracle_mod.lattice(name)
     c, w, T0, two_n, D = L["c"], L["w"], L["T0"], L["two_n"], L["D"]
-    assert L["Q"] == {"D2Q9": 9, "D3Q19": 19, "D3Q39": 39}[name]
-    assert two_n == {"D2Q9": 4, "D3Q19": 4, "D3Q39": 6}[name]
+    assert L["Q"] == {"D2Q9": 9, "D3Q15": 15, "D3Q19": 19, "D3Q39": 39}[name]
+    assert two_n == {"D2Q9": 4, "D3Q15": 4, "D3Q19": 4, "D3Q39": 6}[name]
     assert abs(w.sum() - 1.0) < 1e-15
     for n in range(1, two_n + 2):
         E = moment_tensor(c, w, n)
@@ -143,7 +143,8 @@ def test_hermite_orthogonality(oracle_mod, name):
             err = np.abs(G - ref).max()
             if n + m <= two_n + 1:
                 assert err < 1e-13, (name, n, m, err)
-    bad = {"D3Q19": [(2, 4), (3, 3), (4, 4)], "D3Q39": [(4, 4)], "D2Q9": [(3, 3)]}[name]
+    bad = {"D3Q15": [(2, 4), (3, 3), (4, 4)], "D3Q19": [(2, 4), (3, 3), (4, 4)], "D3Q39": [(4, 4)],
+           "D2Q9": [(3, 3)]}[name]
     for n, m in bad:
         G = np.einsum("i...,i->...", np.einsum("i...,i...->i...",
                       Hs[n].reshape((L["Q"],) + (D,) * n + (1,) * m),
@@ -254,7 +255,7 @@ def _printed_closed_form(L, K, u, Pi):
     return out
 
 
-@pytest.mark.parametrize("name,K", [("D2Q9", 2), ("D2Q9", 3), ("D3Q19", 2), ("D3Q19", 3),
+@pytest.mark.parametrize("name,K", [("D2Q9", 2), ("D2Q9", 3), ("D3Q15", 2), ("D3Q15", 3), ("D3Q19", 2), ("D3Q19", 3),
                                     ("D3Q39", 2), ("D3Q39", 3), ("D3Q39", 4)])
 def test_tensor_path_equals_printed_closed_forms(oracle_mod, name, K):
     L = oracle_mod.lattice(name)
@@ -301,7 +302,7 @@ def test_zero_velocity_reduces_to_old_filter(oracle_mod, name):
     Pi = _rand_pi(D)
     ref = _printed_closed_form(L, 2, np.zeros(D), Pi)
     for K in range(2, L["two_n"]):
-        assert np.abs(oracle_mod.fneq(name, K, np.zeros(D), Pi) - ref).max() < 1e-19
+        assert np.abs(oracle_mod.fneq(name, K, np.zeros(D), Pi) - ref).max() < 2e-15 * np.abs(ref).max()
         assert np.abs(oracle_mod.feq(name, K, 1.3, np.zeros(D)) - 1.3 * L["w"]).max() < 1e-15
 
 
@@ -339,8 +340,8 @@ def test_collision_conserves_and_relaxes_pi(oracle_mod, name):
 # Streaming half of eq. lbe, uniform flow, dimensional reduction.
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("name,dims", [("D2Q9", (5, 4, 1)), ("D3Q19", (4, 3, 5)), ("D3Q39", (7, 2, 3)),
-                                       ("D3Q39", (2, 1, 1))])
+@pytest.mark.parametrize("name,dims", [("D2Q9", (5, 4, 1)), ("D3Q15", (3, 4, 5)), ("D3Q19", (4, 3, 5)),
+                                       ("D3Q39", (7, 2, 3)), ("D3Q39", (2, 1, 1))])
 def test_streaming_moves_population_along_its_velocity(oracle_mod, name, dims):
     """With collision switched off, f_i(x + c_i, t + 1) = f_i(x, t) (eq. lbe),
     periodic in every direction, including boxes shorter than |c|."""
@@ -371,7 +372,7 @@ def test_uniform_flow_is_invariant(oracle_mod, name):
     assert np.abs(sim.populations() - f0).max() < 1e-15
 
 
-@pytest.mark.parametrize("name", ["D3Q19", "D3Q39"])
+@pytest.mark.parametrize("name", ["D3Q15", "D3Q19", "D3Q39"])
 def test_x_only_field_equals_one_dimensional_run(oracle_mod, name):
     """A field that depends on x only stays x-only in a 3-D box, and equals the
     run on an nx x 1 x 1 box bit for bit (the basis of the quasi-1-D parity runs)."""
