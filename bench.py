@@ -28,7 +28,12 @@ METRIC = "MLUPS & % HBM roofline, D3Q19 256³ FP32 vs FP16-storage at stated err
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E peak
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_d3q19_256_fp32.json")
 # what decides the step kernel's machine code: its sources and the compiler flags
-KERNEL_SOURCES = ["csrc/lattice.hpp", "csrc/collide.hpp", "csrc/kernels.hip", "build.py"]
+def _kernel_sources() -> list:
+    """Every source that goes into the device code (all of csrc/ except the
+    host-only C-ABI file), and the build flags."""
+    csrc = os.path.join(ROOT, "paper_2002_02503_amd", "csrc")
+    names = sorted(n for n in os.listdir(csrc) if n.endswith((".hip", ".hpp")) and n != "api.hip")
+    return [f"csrc/{n}" for n in names] + ["build.py"]
 
 
 def log(msg: str) -> None:
@@ -39,7 +44,7 @@ def source_hash() -> str:
     """Hash of the kernel sources and build flags, to tell whether stored
     counters still apply."""
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in _kernel_sources():
         with open(os.path.join(ROOT, "paper_2002_02503_amd", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

@@ -9,9 +9,9 @@
  * (eq. lbe in the introduction, in its regularised form eq. lbe-reg), where
  * the equilibrium is the Hermite expansion eq. hermite and the filtered
  * non-equilibrium part is the Galilean-invariant expansion eq. hermite-coll,
- * both truncated at Hermite order K (default: 3 on D2Q9 and D3Q19, whose
- * isotropy order is 2N = 4, giving eq. filter-1st; 4 on D3Q39, 2N = 6, giving
- * eq. filter-2nd).  rho and u are the zeroth and first moments (eq. mme) and
+ * both truncated at Hermite order K (default: 3 on D2Q9, D3Q15 and D3Q19,
+ * whose isotropy order is 2N = 4, giving eq. filter-1st; 4 on D3Q39, 2N = 6,
+ * giving eq. filter-2nd).  rho and u are the zeroth and first moments (eq. mme) and
  * Pi^neq the non-equilibrium momentum flux (eq. coeff-2 / eq. Pi_def).
  *
  * Conventions for every call:
@@ -40,15 +40,15 @@ extern "C" {
 
 typedef struct lbm_ctx* lbm_t;
 
-/* Velocity sets.  D2Q9 and D3Q19: T0 = 1/3, 2N = 4.  D3Q39: T0 = 2/3, 2N = 6
- * (eq. iso and the lattice catalogue that follows it). */
-typedef enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1, LBM_D3Q39 = 2 } lbm_lattice;
+/* Velocity sets.  D2Q9, D3Q15 and D3Q19: T0 = 1/3, 2N = 4.  D3Q39: T0 = 2/3,
+ * 2N = 6 (eq. iso and the lattice catalogue that follows it). */
+typedef enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1, LBM_D3Q39 = 2, LBM_D3Q15 = 3 } lbm_lattice;
 
 /* Storage type of the populations.  Every type stores S (f_i - w_i): the
  * deviation from the rest weights in units of the weight quantum 1/S (S = 36
- * for D2Q9 and D3Q19, 6480 for D3Q39), so every weight is the exact integer
- * S w_i.  Arithmetic: FP64 computes in double; FP32, FP16 and BF16 compute in
- * float. */
+ * for D2Q9 and D3Q19, 72 for D3Q15, 6480 for D3Q39), so every weight is the
+ * exact integer S w_i.  Arithmetic: FP64 computes in double; FP32, FP16 and
+ * BF16 compute in float. */
 typedef enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16 = 2, LBM_BF16 = 3 } lbm_dtype;
 
 typedef enum {
@@ -60,6 +60,12 @@ typedef enum {
     LBM_ESTATE = -5,   /* call not valid in the current state (e.g. step before init) */
     LBM_ENUMERIC = -6  /* non-finite or non-positive density found by lbm_totals */
 } lbm_status;
+
+/* Collision operators (lbm_set_collision). */
+typedef enum {
+    LBM_COLLISION_FILTERED = 0,  /* eq. post-1 with the truncated eq. hermite-coll (the default) */
+    LBM_COLLISION_BGK = 1        /* eq. BGK, f' = f - (f - f^eq)/tau, with the same truncated f^eq */
+} lbm_collision;
 
 /* Step-kernel variants for a single box (lbm_set_kernel). */
 typedef enum {
@@ -81,6 +87,8 @@ typedef struct {
     int32_t block, grid;         /* launch shape in use (threads per block; batched grid size, 0 = one block per tile) */
     int32_t graph_chunk;         /* steps per captured graph */
     int32_t kernel;              /* step kernel in use (lbm_kernel, never AUTO) */
+    int32_t collision;           /* lbm_collision in use */
+    double theta;                /* weight of the energy-flux term (0: none) */
 } lbm_info;
 
 /* Create a single periodic box (eq. lbe on an nx*ny*nz torus).
@@ -100,8 +108,22 @@ lbm_status lbm_create_batch(lbm_t* out, int32_t lattice, int32_t nbox, const int
 
 /* Hermite truncation order K of both expansions, 2 <= K <= 2N - 1 (the
  * truncation rule after eq. hermite-coll).  K = 2 is the zero-velocity filter
- * eq. filter-Pi with the second-order equilibrium.  Only before lbm_init. */
+ * eq. filter-Pi with the second-order equilibrium.  With BGK, K is the order
+ * of the equilibrium.  K = 2 is rejected while an energy-flux weight theta != 0
+ * is set.  Only before lbm_init. */
 lbm_status lbm_set_hermite_order(lbm_t h, int32_t K);
+
+/* Collision operator and the weight theta of the energy-flux term (eq. pq,
+ * Discussion section).  collision: LBM_COLLISION_FILTERED (default) or
+ * LBM_COLLISION_BGK.  theta != 0 adds theta times the energy-flux part to the
+ * filtered non-equilibrium part: the compact form eq. filter-Q, with f^eq / rho
+ * so that it reduces to the theta term of eq. filter2 at u = 0, expanded in
+ * Hermite tensors and truncated at the same order K, built on the relative
+ * non-equilibrium energy flux eq. Q_def.  It needs the filtered operator and
+ * K >= 3 (its series starts at the third order).  theta must be finite.
+ * Errors: LBM_EINVAL (unknown collision, theta not finite, theta != 0 with BGK
+ * or with K = 2), LBM_ESTATE after lbm_init. */
+lbm_status lbm_set_collision(lbm_t h, int32_t collision, double theta);
 
 /* Run device work on `hip_stream` (a hipStream_t; NULL = the null stream).
  * The caller keeps ownership of the stream; it must outlive the handle's use. */
@@ -190,12 +212,13 @@ lbm_status lbm_checkpoint_bytes(lbm_t h, size_t* bytes);
 /* Copy the state to host memory `buf` of at least lbm_checkpoint_bytes(): a
  * 64-byte header (lattice, dtype, K, geometry hash, t) followed by the stored
  * values S (f_i - w_i) in the layout described at lbm_state_bytes (S = 36 for
- * D2Q9 and D3Q19, 6480 for D3Q39). */
+ * D2Q9 and D3Q19, 72 for D3Q15, 6480 for D3Q39). */
 lbm_status lbm_get_state(lbm_t h, void* buf, size_t bytes);
 
 /* Restore a state written by lbm_get_state on a handle of the same lattice,
  * dtype, K and geometry.  The next steps reproduce the original run bit for
- * bit. */
+ * bit when the handle also has the same collision operator and theta (these
+ * are not recorded: the populations are valid input to any operator). */
 lbm_status lbm_set_state(lbm_t h, const void* buf, size_t bytes);
 
 /* Describe the handle. */

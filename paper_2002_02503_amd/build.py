@@ -6,7 +6,9 @@ where one source expression writes a * b + c (-ffp-contract=on), never across
 statements in the backend, so every kernel form of the step (one site per
 lane, several sites per lane, batched) rounds the same expressions the same
 way and computes the same bits.  The translation units are
-compiled in parallel and linked into ``paper_2002_02503_amd/liblbm.so``.
+compiled in parallel and linked into ``paper_2002_02503_amd/liblbm.so``.  The
+step kernels' template instances are spread over small generated units (see
+INSTANCE_GROUPS) so that the build runs in parallel.
 """
 from __future__ import annotations
 
@@ -20,7 +22,13 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "liblbm.so")
-SOURCES = ["kernels.hip", "step.hip", "step_batch.hip", "api.hip"]
+SOURCES = ["kernels.hip", "api.hip"]
+STORAGE = ["double", "float", "_Float16", "bf16_t"]
+# Step-kernel instances, one translation unit per group (lattice, storage
+# types): the large D3Q39 instances get a unit per storage type so that the
+# units compile in parallel in similar times.
+INSTANCE_GROUPS = ([("D2Q9", STORAGE), ("D3Q15", STORAGE), ("D3Q19", STORAGE)]
+                   + [("D3Q39", [s]) for s in STORAGE])
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -30,7 +38,7 @@ FLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++20", "-fPIC", "-Wall", "-ffp-
 
 
 def _compile(src: str, obj: str) -> None:
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     # hipcc's host pass warns about the device-only target feature; drop that noise
     noise = ("packed-fp32-ops", "warning: unknown target feature", "1 warning generated")
@@ -41,12 +49,38 @@ def _compile(src: str, obj: str) -> None:
         sys.stderr.write(err + "\n")
 
 
+def _instance_units(gendir: str) -> list:
+    """Write the step-kernel instance units: each includes step.hpp (single
+    box) or step_batch.hpp (batch) and instantiates the launchers of one group
+    of (lattice, storage type) pairs."""
+    units = []
+    for lat, types in INSTANCE_GROUPS:
+        tag = lat.lower() + ("" if len(types) > 1 else "_" + types[0].strip("_").lower())
+        for family, header, macro in [("step", "step.hpp", "LBM_DECLARE_STEP_INSTANCES"),
+                                      ("batch", "step_batch.hpp", "LBM_DECLARE_BATCH_INSTANCES")]:
+            path = os.path.join(gendir, f"{family}_{tag}.hip")
+            lines = [f"// {family} kernels of {lat} ({', '.join(types)}); written by build.py",
+                     f'#include "{header}"', "namespace lbm {"]
+            lines += [f"{macro}(, {lat}, {t})" for t in types]
+            lines += ["}  // namespace lbm", ""]
+            text = "\n".join(lines)
+            old = open(path).read() if os.path.exists(path) else None
+            if old != text:
+                with open(path, "w") as f:
+                    f.write(text)
+            units.append(path)
+    return units
+
+
 def build(out: str = LIB) -> str:
     objdir = os.path.join(PKG, "_build")
-    os.makedirs(objdir, exist_ok=True)
-    objs = [os.path.join(objdir, s.replace(".hip", ".o")) for s in SOURCES]
-    with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        list(ex.map(_compile, SOURCES, objs))
+    gendir = os.path.join(objdir, "gen")
+    os.makedirs(gendir, exist_ok=True)
+    srcs = [os.path.join(CSRC, s) for s in SOURCES] + _instance_units(gendir)
+    objs = [os.path.join(objdir, os.path.basename(s).replace(".hip", ".o")) for s in srcs]
+    workers = min(len(srcs), max(1, os.cpu_count() or 1), 16)
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        list(ex.map(_compile, srcs, objs))
     tmp = out + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)

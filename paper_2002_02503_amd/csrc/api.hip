@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "lattice.hpp"
 #include "lbm.h"
 
 using namespace lbm;
@@ -67,6 +68,8 @@ static_assert(sizeof(CkptHeader) == 64, "checkpoint header layout");
 
 struct lbm_ctx {
     int lattice = 0, dtype = 0, K = 0;
+    int collision = LBM_COLLISION_FILTERED;
+    double theta = 0.0;             // weight of the energy-flux term
     LatticeInfo lat;
     int nbox = 0;
     std::vector<int64_t> dims;      // nbox * 3
@@ -117,6 +120,13 @@ int row_wave_sites(const lbm_ctx* h)
     const int64_t nx = h->dims[0];
     if (V == 0 || nx % V != 0 || nx / V > 64) return 0;
     return V;
+}
+
+// Collision kind of the step kernels (lattice.hpp, CollisionKind).
+int step_kind(const lbm_ctx* h)
+{
+    if (h->collision == LBM_COLLISION_BGK) return kBGK;
+    return h->theta != 0.0 ? kFilteredQ : kFiltered;
 }
 
 int effective_kernel(const lbm_ctx* h)
@@ -371,7 +381,8 @@ hipError_t launch_one(lbm_ctx* h, int src_idx, hipStream_t s)
         geo.lanes_per_row = geo.nx / V;
         geo.rows_per_wave = 64 / geo.lanes_per_row;
         geo.nrows = geo.ny * geo.nz;
-        return launch_step_vec(h->lattice, h->dtype, h->K, src, dst, geo, 1.0 - 1.0 / h->tau[0], s);
+        return launch_step_vec(h->lattice, h->dtype, h->K, step_kind(h), src, dst, geo, 1.0 - 1.0 / h->tau[0],
+                               h->theta, s);
     }
     if (is_single(h)) {
         StepGeom geo;
@@ -379,10 +390,11 @@ hipError_t launch_one(lbm_ctx* h, int src_idx, hipStream_t s)
         geo.ny = int(h->dims[1]);
         geo.nz = int(h->dims[2]);
         geo.xblocks = (geo.nx + block - 1) / block;
-        return launch_step(h->lattice, h->dtype, h->K, src, dst, geo, 1.0 - 1.0 / h->tau[0], block, s);
+        return launch_step(h->lattice, h->dtype, h->K, step_kind(h), src, dst, geo, 1.0 - 1.0 / h->tau[0],
+                           h->theta, block, s);
     }
-    return launch_step_batch(h->lattice, h->dtype, h->K, src, dst, h->d_tiles, h->ntiles, h->d_boxes, block,
-                             h->grid, s);
+    return launch_step_batch(h->lattice, h->dtype, h->K, step_kind(h), src, dst, h->d_tiles, h->ntiles,
+                             h->d_boxes, h->theta, block, h->grid, s);
 }
 
 lbm_status build_graph(lbm_ctx* h, int parity)
@@ -453,8 +465,26 @@ lbm_status lbm_set_hermite_order(lbm_t h, int32_t K)
     if (lbm_status st = check_handle(h)) return st;
     if (K < 2 || K > h->lat.k_max)
         return fail(LBM_EINVAL, "Hermite order K = %d outside [2, 2N-1 = %d]", K, h->lat.k_max);
+    if (K < 3 && h->theta != 0.0)
+        return fail(LBM_EINVAL, "the energy-flux term (theta != 0) needs K >= 3");
     if (h->initialized) return fail(LBM_ESTATE, "set the Hermite order before lbm_init");
     h->K = K;
+    drop_graphs(h);
+    return LBM_OK;
+}
+
+lbm_status lbm_set_collision(lbm_t h, int32_t collision, double theta)
+{
+    if (lbm_status st = check_handle(h)) return st;
+    if (collision != LBM_COLLISION_FILTERED && collision != LBM_COLLISION_BGK)
+        return fail(LBM_EINVAL, "unknown collision operator %d", collision);
+    if (!std::isfinite(theta)) return fail(LBM_EINVAL, "theta must be finite");
+    if (theta != 0.0 && collision != LBM_COLLISION_FILTERED)
+        return fail(LBM_EINVAL, "the energy-flux term (theta != 0) belongs to the filtered operator");
+    if (theta != 0.0 && h->K < 3) return fail(LBM_EINVAL, "the energy-flux term (theta != 0) needs K >= 3");
+    if (h->initialized) return fail(LBM_ESTATE, "set the collision operator before lbm_init");
+    h->collision = collision;
+    h->theta = theta;
     drop_graphs(h);
     return LBM_OK;
 }
@@ -601,8 +631,9 @@ struct LaunchChoice {
 std::string tune_key(const lbm_ctx* h)
 {
     char buf[256];
-    snprintf(buf, sizeof(buf), "lattice=%d dtype=%d K=%d nbox=%d nsites=%lld geometry=%016llx", h->lattice,
-             h->dtype, h->K, h->nbox, (long long)h->nsites, (unsigned long long)geometry_hash(h));
+    snprintf(buf, sizeof(buf), "lattice=%d dtype=%d K=%d kind=%d nbox=%d nsites=%lld geometry=%016llx",
+             h->lattice, h->dtype, h->K, step_kind(h), h->nbox, (long long)h->nsites,
+             (unsigned long long)geometry_hash(h));
     return buf;
 }
 
@@ -880,6 +911,8 @@ lbm_status lbm_get_info(lbm_t h, lbm_info* info)
     info->grid = h->grid;
     info->graph_chunk = h->graph_chunk;
     info->kernel = effective_kernel(h);
+    info->collision = h->collision;
+    info->theta = h->theta;
     return LBM_OK;
 }
 

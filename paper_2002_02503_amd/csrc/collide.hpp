@@ -73,10 +73,65 @@ __device__ __forceinline__ R cquad(R qxx, R qyy, R qzz, R qxy, R qxz, R qyz)
     return acc;
 }
 
-template <class L, int K, bool PROJ, class R>
-__device__ __forceinline__ void collide_site(R (&G)[L::Q], R omega)
+// Collision kinds.  kFiltered is the operator above.  kBGK is eq. BGK with the
+// same truncated equilibrium: G' = G^eq + (1 - 1/tau)(G - G^eq).  kFilteredQ
+// adds theta times the energy-flux part of eq. pq: the compact form
+// eq. filter-Q (with f^eq / rho, so that it is the theta term of eq. filter2
+// at u = 0) expanded in Hermite tensors and truncated at the same K.  Three
+// t-derivatives of the generating function, contracted with the relative
+// energy flux Qt (eq. Q_def) and evaluated along t = V, give
+//     fhat^q_i = (w_i / 6 T0^3) [d0 P_{K-3} + d1 P_{K-4} + d2 P_{K-5}],
+//     d0 = Qt.ccc - 3 T0 c.qt,  d1 = -3 c.(Qt.u).c + 3 T0 u.qt,  d2 = 3 c.(Qt:uu),
+// with qt_c = sum_a Qt_aac (the next term, -Qt:uuu P_{K-6}, needs K >= 6).
+// Because f - f^eq carries no mass or momentum,
+//     Qt = sum c c c (f - f^eq) - (u Pi + Pi u + the third permutation).
+// (The kind codes, CollisionKind, are in lattice.hpp.)
+
+// Third moment accumulators, stored by the number of x, y and z indices.
+template <class R>
+struct Sym3 {
+    R xxx, xxy, xxz, xyy, xyz, xzz, yyy, yyz, yzz, zzz;
+};
+
+// acc += v * c c c for a compile-time c, component by component
+template <int X, int Y, int Z, class R>
+__device__ __forceinline__ void add_ccc(Sym3<R>& t, R v)
+{
+    if constexpr (X * X * X != 0) t.xxx += R(X * X * X) * v;
+    if constexpr (X * X * Y != 0) t.xxy += R(X * X * Y) * v;
+    if constexpr (X * X * Z != 0) t.xxz += R(X * X * Z) * v;
+    if constexpr (X * Y * Y != 0) t.xyy += R(X * Y * Y) * v;
+    if constexpr (X * Y * Z != 0) t.xyz += R(X * Y * Z) * v;
+    if constexpr (X * Z * Z != 0) t.xzz += R(X * Z * Z) * v;
+    if constexpr (Y * Y * Y != 0) t.yyy += R(Y * Y * Y) * v;
+    if constexpr (Y * Y * Z != 0) t.yyz += R(Y * Y * Z) * v;
+    if constexpr (Y * Z * Z != 0) t.yzz += R(Y * Z * Z) * v;
+    if constexpr (Z * Z * Z != 0) t.zzz += R(Z * Z * Z) * v;
+}
+
+// t : c c c (full contraction with a symmetric tensor) for a compile-time c
+template <int X, int Y, int Z, class R>
+__device__ __forceinline__ R ccc_dot(const Sym3<R>& t)
+{
+    R acc = R(-0.0);
+    if constexpr (X * X * X != 0) acc += R(X * X * X) * t.xxx;
+    if constexpr (X * X * Y != 0) acc += R(3 * X * X * Y) * t.xxy;
+    if constexpr (X * X * Z != 0) acc += R(3 * X * X * Z) * t.xxz;
+    if constexpr (X * Y * Y != 0) acc += R(3 * X * Y * Y) * t.xyy;
+    if constexpr (X * Y * Z != 0) acc += R(6 * X * Y * Z) * t.xyz;
+    if constexpr (X * Z * Z != 0) acc += R(3 * X * Z * Z) * t.xzz;
+    if constexpr (Y * Y * Y != 0) acc += R(Y * Y * Y) * t.yyy;
+    if constexpr (Y * Y * Z != 0) acc += R(3 * Y * Y * Z) * t.yyz;
+    if constexpr (Y * Z * Z != 0) acc += R(3 * Y * Z * Z) * t.yzz;
+    if constexpr (Z * Z * Z != 0) acc += R(Z * Z * Z) * t.zzz;
+    return acc;
+}
+
+template <class L, int K, int KIND, bool PROJ, class R>
+__device__ __forceinline__ void collide_site(R (&G)[L::Q], R omega, R theta)
 {
     static_assert(K >= 2 && K <= L::K_MAX, "Hermite order outside 2..2N-1");
+    static_assert(KIND == kFiltered || KIND == kBGK || (KIND == kFilteredQ && K >= 3), "collision kind");
     constexpr int NP = (L::Q - 1) / 2;  // opposite pairs (2p+1, 2p+2)
     constexpr bool D3 = (L::D == 3);
     constexpr R IT0 = R(L::INV_T0);
@@ -145,61 +200,170 @@ __device__ __forceinline__ void collide_site(R (&G)[L::Q], R omega)
     const R Cs = D3 ? R(0.5) * (ux * bqx + uy * bqy + uz * bqz) : R(0.5) * (ux * bqx + uy * bqy);
     const R om2 = omega * R(0.5) * IT0;
 
+    // Per pair: a, h_n and the even / odd parts of P_m = sum_{n<=m} h_n/n!.
+    // Pe_0 = Pe_1 = 1, Pe_2 = Pe_3 = 1 + h2/2, Pe_4 = Pe_5 = Pe_2 + h4/24;
+    // Po_1 = Po_2 = a, Po_3 = Po_4 = a + h3/6, Po_5 = Po_3 + h5/120.
+    // Ee = Pe_K - 1 and Po = Po_K.
+    auto eq_parts = [&](R a, R& Ee, R& Po) {
+        const R h2 = a * a - v;
+        Ee = R(0.5) * h2;
+        if constexpr (K == 2) {
+            Po = a;
+        } else {
+            const R h3 = a * (h2 - R(2) * v);
+            Po = a + R(1.0 / 6.0) * h3;
+            if constexpr (K >= 4) {
+                const R h4 = a * h3 - R(3) * v * h2;
+                Ee = Ee + R(1.0 / 24.0) * h4;
+                if constexpr (K == 5) {
+                    const R h5 = a * h4 - R(4) * v * h3;
+                    Po = Po + R(1.0 / 120.0) * h5;
+                }
+            }
+        }
+    };
+
+    // Energy flux (kFilteredQ): Qt scaled by omega theta / (6 T0^3), the
+    // factor of fhat^q in stored units.
+    Sym3<R> Qs{};
+    R qsx = R(0), qsy = R(0), qsz = R(0);            // qt_c
+    R rxx = R(0), ryy = R(0), rzz = R(0), rxy = R(0), rxz = R(0), ryz = R(0);  // Qt.u
+    R rsx = R(0), rsy = R(0), rsz = R(0);            // Qt:uu
+    R d1u = R(0);                                     // 3 T0 u.qt
+    if constexpr (KIND == kFilteredQ) {
+        // S sum c c c (G - G^eq): only the odd part G_+ - G_- of each pair counts
+        Sym3<R> t{NZ, NZ, NZ, NZ, NZ, NZ, NZ, NZ, NZ, NZ};
+        unroll<NP>([&](auto P) {
+            constexpr int i = 2 * decltype(P)::value + 1;
+            constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
+            R Ee, Po;
+            eq_parts(cdot<cx, cy, cz>(uqx, uqy, uqz), Ee, Po);
+            const R dneq = (G[i] - G[i + 1]) - R(2 * L::W[i]) * rho * Po;
+            add_ccc<cx, cy, cz>(t, dneq);
+        });
+        const R cq = omega * theta * R(1.0 / (6.0 * L::T0 * L::T0 * L::T0));
+        const R cs = cq * IS;
+        const R Pxx = qxx * T0, Pyy = qyy * T0, Pxy = qxy * T0;
+        const R Pzz = qzz * T0, Pxz = qxz * T0, Pyz = qyz * T0;
+        Qs.xxx = t.xxx * cs - cq * (R(3) * ux * Pxx);
+        Qs.xxy = t.xxy * cs - cq * (R(2) * ux * Pxy + uy * Pxx);
+        Qs.xyy = t.xyy * cs - cq * (R(2) * uy * Pxy + ux * Pyy);
+        Qs.yyy = t.yyy * cs - cq * (R(3) * uy * Pyy);
+        if constexpr (D3) {
+            Qs.xxz = t.xxz * cs - cq * (R(2) * ux * Pxz + uz * Pxx);
+            Qs.xyz = t.xyz * cs - cq * (ux * Pyz + uy * Pxz + uz * Pxy);
+            Qs.xzz = t.xzz * cs - cq * (R(2) * uz * Pxz + ux * Pzz);
+            Qs.yyz = t.yyz * cs - cq * (R(2) * uy * Pyz + uz * Pyy);
+            Qs.yzz = t.yzz * cs - cq * (R(2) * uz * Pyz + uy * Pzz);
+            Qs.zzz = t.zzz * cs - cq * (R(3) * uz * Pzz);
+        }
+        qsx = Qs.xxx + Qs.xyy + Qs.xzz;
+        qsy = Qs.xxy + Qs.yyy + Qs.yzz;
+        qsz = Qs.xxz + Qs.yyz + Qs.zzz;
+        if constexpr (K >= 4) {
+            rxx = Qs.xxx * ux + Qs.xxy * uy + Qs.xxz * uz;
+            ryy = Qs.xyy * ux + Qs.yyy * uy + Qs.yyz * uz;
+            rzz = Qs.xzz * ux + Qs.yzz * uy + Qs.zzz * uz;
+            rxy = Qs.xxy * ux + Qs.xyy * uy + Qs.xyz * uz;
+            rxz = Qs.xxz * ux + Qs.xyz * uy + Qs.xzz * uz;
+            ryz = Qs.xyz * ux + Qs.yyz * uy + Qs.yzz * uz;
+            d1u = R(3) * T0 * (qsx * ux + qsy * uy + qsz * uz);
+        }
+        if constexpr (K >= 5) {
+            rsx = rxx * ux + rxy * uy + rxz * uz;
+            rsy = rxy * ux + ryy * uy + ryz * uz;
+            rsz = rxz * ux + ryz * uy + rzz * uz;
+        }
+    }
+
     // Each pair shares a, h_n and A; a, B and the odd h_n change sign under
-    // c -> -c.  With Pe / Po the even / odd parts of P_m = sum_{n<=m} h_n/n!,
+    // c -> -c.  With Pe / Po the even / odd parts of P_m,
     //   N_even = A Pe_{K-2} - B Po_{K-3} + C Pe_{K-4},
     //   N_odd  = A Po_{K-2} - B Pe_{K-3} + C Po_{K-4},
     //   G_+- = W [(rho-1) + rho (Pe_K - 1) + om2 N_even] +- W [rho Po_K + om2 N_odd].
-    // Pe_0 = Pe_1 = 1, Pe_2 = Pe_3 = 1 + h2/2, Pe_4 = Pe_5 = Pe_2 + h4/24;
-    // Po_1 = Po_2 = a, Po_3 = Po_4 = a + h3/6, Po_5 = Po_3 + h5/120.
     {
         // rest particle: a = 0, B = 0, A = -tr Pi, h2 = -v, h3 = 0, h4 = 3 v^2
         const R A0 = -trP;
         const R Ee2 = R(-0.5) * v;
+        R Ee = Ee2;
+        if constexpr (K >= 4) Ee = Ee2 + R(0.125) * v * v;
         R Xe;
-        if constexpr (K <= 3) {
-            Xe = drho + rho * Ee2 + om2 * A0;
+        if constexpr (KIND == kBGK) {
+            const R geq = R(L::W[0]) * (drho + rho * Ee);
+            Xe = geq + omega * (G[0] - geq);
         } else {
-            const R Ee4 = Ee2 + R(0.125) * v * v;
-            Xe = drho + rho * Ee4 + om2 * (A0 + A0 * Ee2 + Cs);
+            if constexpr (K <= 3) {
+                Xe = drho + rho * Ee + om2 * A0;
+            } else {
+                Xe = drho + rho * Ee + om2 * (A0 + A0 * Ee2 + Cs);
+            }
+            if constexpr (KIND == kFilteredQ && K >= 4) Xe += d1u;
+            Xe = R(L::W[0]) * Xe;
         }
-        G[0] = R(L::W[0]) * Xe;
+        G[0] = Xe;
     }
     unroll<NP>([&](auto P) {
         constexpr int i = 2 * decltype(P)::value + 1;
         constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
         constexpr R Wi = R(L::W[i]);
         const R a = cdot<cx, cy, cz>(uqx, uqy, uqz);
-        const R A = cquad<cx, cy, cz>(qxx, qyy, qzz, qxy, qxz, qyz) - trP;
-        const R h2 = a * a - v;
-        const R Ee2 = R(0.5) * h2;
-        R Xe, Xo;
-        if constexpr (K == 2) {
-            Xe = drho + rho * Ee2 + om2 * A;
-            Xo = rho * a;
+        if constexpr (KIND == kBGK) {
+            R Ee, Po;
+            eq_parts(a, Ee, Po);
+            const R Xe = drho + rho * Ee;
+            const R Xo = rho * Po;
+            const R gp = Wi * (Xe + Xo);
+            const R gm = Wi * (Xe - Xo);
+            G[i] = gp + omega * (G[i] - gp);
+            G[i + 1] = gm + omega * (G[i + 1] - gm);
         } else {
-            const R B = cdot<cx, cy, cz>(bqx, bqy, bqz);
-            const R h3 = a * (h2 - R(2) * v);
-            const R Po3 = a + R(1.0 / 6.0) * h3;
-            if constexpr (K == 3) {
+            const R A = cquad<cx, cy, cz>(qxx, qyy, qzz, qxy, qxz, qyz) - trP;
+            const R h2 = a * a - v;
+            const R Ee2 = R(0.5) * h2;
+            R Xe, Xo;
+            if constexpr (K == 2) {
                 Xe = drho + rho * Ee2 + om2 * A;
-                Xo = rho * Po3 + om2 * (A * a - B);
+                Xo = rho * a;
             } else {
-                const R h4 = a * h3 - R(3) * v * h2;
-                const R Ee4 = Ee2 + R(1.0 / 24.0) * h4;
-                const R Ne = A + A * Ee2 - B * a + Cs;
-                Xe = drho + rho * Ee4 + om2 * Ne;
-                if constexpr (K == 4) {
+                const R B = cdot<cx, cy, cz>(bqx, bqy, bqz);
+                const R h3 = a * (h2 - R(2) * v);
+                const R Po3 = a + R(1.0 / 6.0) * h3;
+                if constexpr (K == 3) {
+                    Xe = drho + rho * Ee2 + om2 * A;
                     Xo = rho * Po3 + om2 * (A * a - B);
                 } else {
-                    const R h5 = a * h4 - R(4) * v * h3;
-                    const R Po5 = Po3 + R(1.0 / 120.0) * h5;
-                    Xo = rho * Po5 + om2 * (A * Po3 - B - B * Ee2 + Cs * a);
+                    const R h4 = a * h3 - R(3) * v * h2;
+                    const R Ee4 = Ee2 + R(1.0 / 24.0) * h4;
+                    const R Ne = A + A * Ee2 - B * a + Cs;
+                    Xe = drho + rho * Ee4 + om2 * Ne;
+                    if constexpr (K == 4) {
+                        Xo = rho * Po3 + om2 * (A * a - B);
+                    } else {
+                        const R h5 = a * h4 - R(4) * v * h3;
+                        const R Po5 = Po3 + R(1.0 / 120.0) * h5;
+                        Xo = rho * Po5 + om2 * (A * Po3 - B - B * Ee2 + Cs * a);
+                    }
+                }
+                if constexpr (KIND == kFilteredQ) {
+                    // d0 (odd), d1 (even), d2 (odd) of the energy-flux part
+                    const R d0 = ccc_dot<cx, cy, cz>(Qs) - R(3) * T0 * cdot<cx, cy, cz>(qsx, qsy, qsz);
+                    if constexpr (K == 3) {
+                        Xo += d0;
+                    } else {
+                        const R d1 = d1u - R(3) * cquad<cx, cy, cz>(rxx, ryy, rzz, rxy, rxz, ryz);
+                        Xe += d0 * a + d1;
+                        if constexpr (K == 4) {
+                            Xo += d0;
+                        } else {
+                            const R d2 = R(3) * cdot<cx, cy, cz>(rsx, rsy, rsz);
+                            Xo += d0 * (R(1) + Ee2) + d1 * a + d2;
+                        }
+                    }
                 }
             }
+            G[i] = Wi * (Xe + Xo);
+            G[i + 1] = Wi * (Xe - Xo);
         }
-        G[i] = Wi * (Xe + Xo);
-        G[i + 1] = Wi * (Xe - Xo);
     });
 
     if constexpr (PROJ) {

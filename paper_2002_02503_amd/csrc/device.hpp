@@ -228,47 +228,84 @@ constexpr int vec_sites()
 }
 
 // ---------------------------------------------------------------------------
-// Dispatch from runtime (lattice, dtype, K) to template instances.
+// Dispatch from runtime (dtype, K, collision kind) to template instances of
+// one lattice, and from a runtime lattice to that.  The callee gets
+// (L{}, (S*)nullptr, integral_constant K, integral_constant kind).  The
+// energy-flux kind exists for K >= 3 only (its Hermite series starts at
+// n = 3).
 // ---------------------------------------------------------------------------
 
-template <class L, class S, class F>
-hipError_t by_k(int K, F&& f)
+template <int V>
+using ic = std::integral_constant<int, V>;
+
+template <class L, class S, int KK, class F>
+hipError_t by_kind(int kind, F&& f)
 {
-    switch (K) {
-    case 2: return f(L{}, (S*)nullptr, std::integral_constant<int, 2>{});
-    case 3: return f(L{}, (S*)nullptr, std::integral_constant<int, 3>{});
-    case 4:
-        if constexpr (L::K_MAX >= 4) return f(L{}, (S*)nullptr, std::integral_constant<int, 4>{});
-        break;
-    case 5:
-        if constexpr (L::K_MAX >= 5) return f(L{}, (S*)nullptr, std::integral_constant<int, 5>{});
+    switch (kind) {
+    case kFiltered: return f(L{}, (S*)nullptr, ic<KK>{}, ic<kFiltered>{});
+    case kBGK: return f(L{}, (S*)nullptr, ic<KK>{}, ic<kBGK>{});
+    case kFilteredQ:
+        if constexpr (KK >= 3) return f(L{}, (S*)nullptr, ic<KK>{}, ic<kFilteredQ>{});
         break;
     default: break;
     }
     return hipErrorInvalidValue;
 }
 
+template <class L, class S, class F>
+hipError_t by_k(int K, int kind, F&& f)
+{
+    switch (K) {
+    case 2: return by_kind<L, S, 2>(kind, f);
+    case 3: return by_kind<L, S, 3>(kind, f);
+    case 4:
+        if constexpr (L::K_MAX >= 4) return by_kind<L, S, 4>(kind, f);
+        break;
+    case 5:
+        if constexpr (L::K_MAX >= 5) return by_kind<L, S, 5>(kind, f);
+        break;
+    default: break;
+    }
+    return hipErrorInvalidValue;
+}
+
+// (K, kind) for a fixed (lattice, storage type).
+template <class L, class S, class F>
+hipError_t dispatch_pair(int K, int kind, F&& f)
+{
+    return by_k<L, S>(K, kind, f);
+}
+
 template <class L, class F>
-hipError_t by_dtype(int dtype, int K, F&& f)
+hipError_t dispatch_lattice(int dtype, int K, int kind, F&& f)
 {
     switch (dtype) {
-    case 0: return by_k<L, double>(K, f);
-    case 1: return by_k<L, float>(K, f);
-    case 2: return by_k<L, _Float16>(K, f);
-    case 3: return by_k<L, bf16_t>(K, f);
+    case 0: return by_k<L, double>(K, kind, f);
+    case 1: return by_k<L, float>(K, kind, f);
+    case 2: return by_k<L, _Float16>(K, kind, f);
+    case 3: return by_k<L, bf16_t>(K, kind, f);
     default: return hipErrorInvalidValue;
     }
 }
 
 template <class F>
-hipError_t dispatch(int lat, int dtype, int K, F&& f)
+hipError_t dispatch_kind(int lat, int dtype, int K, int kind, F&& f)
 {
     switch (lat) {
-    case kD2Q9: return by_dtype<D2Q9>(dtype, K, f);
-    case kD3Q19: return by_dtype<D3Q19>(dtype, K, f);
-    case kD3Q39: return by_dtype<D3Q39>(dtype, K, f);
+    case kD2Q9: return dispatch_lattice<D2Q9>(dtype, K, kind, f);
+    case kD3Q15: return dispatch_lattice<D3Q15>(dtype, K, kind, f);
+    case kD3Q19: return dispatch_lattice<D3Q19>(dtype, K, kind, f);
+    case kD3Q39: return dispatch_lattice<D3Q39>(dtype, K, kind, f);
     default: return hipErrorInvalidValue;
     }
+}
+
+// (lattice, dtype, K) for callees that take (L{}, (S*)nullptr, K constant).
+template <class F>
+hipError_t dispatch(int lat, int dtype, int K, F&& f)
+{
+    return dispatch_kind(lat, dtype, K, kFiltered,
+                         [&](auto Lt, auto* Sp, auto Kc, auto) -> hipError_t { return f(Lt, Sp, Kc); });
 }
 
 // (lattice, dtype) only: K fixed to 2, ignored by the callee.

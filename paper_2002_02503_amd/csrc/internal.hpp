@@ -63,15 +63,17 @@ struct ChunkDesc {
 hipError_t launch_init(int lat, int dtype, int K, const double* rho, const double* u, void* dst,
                        const ChunkDesc* chunks, int nchunks, const BoxDesc* boxes, long long nsites,
                        hipStream_t s);
-hipError_t launch_step(int lat, int dtype, int K, const void* src, void* dst, const StepGeom& geo,
-                       double omega, int block, hipStream_t s);
+// The fused step.  kind: collision kind (collide.hpp: 0 filtered, 1 BGK,
+// 2 filtered with the energy-flux term of weight theta).
+hipError_t launch_step(int lat, int dtype, int K, int kind, const void* src, void* dst, const StepGeom& geo,
+                       double omega, double theta, int block, hipStream_t s);
 // Sites per lane of the row-wave kernel for (lattice, dtype), 0 if that pair
 // has no row-wave form (a velocity component as large as V).
 int vec_sites_per_lane(int lat, int dtype);
-hipError_t launch_step_vec(int lat, int dtype, int K, const void* src, void* dst, const VecGeom& geo, double omega,
-                           hipStream_t s);
-hipError_t launch_step_batch(int lat, int dtype, int K, const void* src, void* dst, const TileDesc* tiles,
-                             int ntiles, const BoxDesc* boxes, int block, int grid, hipStream_t s);
+hipError_t launch_step_vec(int lat, int dtype, int K, int kind, const void* src, void* dst, const VecGeom& geo,
+                           double omega, double theta, hipStream_t s);
+hipError_t launch_step_batch(int lat, int dtype, int K, int kind, const void* src, void* dst, const TileDesc* tiles,
+                             int ntiles, const BoxDesc* boxes, double theta, int block, int grid, hipStream_t s);
 hipError_t launch_moments(int lat, int dtype, const void* src, double* rho, double* u, const ChunkDesc* chunks,
                           int nchunks, const BoxDesc* boxes, long long nsites, hipStream_t s);
 hipError_t launch_totals(int lat, int dtype, const void* src, const ChunkDesc* chunks, int nchunks,

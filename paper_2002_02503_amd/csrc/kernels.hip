@@ -12,6 +12,7 @@
 // matrix cores: every population is read once (pull form of eq. lbe, periodic
 // wrap) and written once, and the collision runs entirely in registers.
 #include "device.hpp"
+#include "step_launch.hpp"
 
 namespace lbm {
 
@@ -295,6 +296,61 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s)
 }
 
 // ---------------------------------------------------------------------------
+// Runtime-lattice entry points of the step kernels (instances compiled per
+// lattice in step_<lattice>.hip and batch_<lattice>.hip).
+// ---------------------------------------------------------------------------
+
+// Calls f(L{}, (S*)nullptr) for a runtime (lattice, dtype).
+template <class F>
+static hipError_t by_pair(int lat, int dtype, F&& f)
+{
+    return dispatch_kind(lat, dtype, 2, kFiltered,
+                         [&](auto Lt, auto* Sp, auto, auto) -> hipError_t { return f(Lt, Sp); });
+}
+
+hipError_t launch_step(int lat, int dtype, int K, int kind, const void* src, void* dst, const StepGeom& geo,
+                       double omega, double theta, int block, hipStream_t s)
+{
+    return by_pair(lat, dtype, [&](auto Lt, auto* Sp) {
+        using L = decltype(Lt);
+        using S = std::remove_pointer_t<decltype(Sp)>;
+        return launch_step_l<L, S>(K, kind, src, dst, geo, omega, theta, block, s);
+    });
+}
+
+int vec_sites_per_lane(int lat, int dtype)
+{
+    int v = 0;
+    (void)by_pair(lat, dtype, [&](auto Lt, auto* Sp) {
+        using L = decltype(Lt);
+        using S = std::remove_pointer_t<decltype(Sp)>;
+        v = vec_sites_l<L, S>();
+        return hipSuccess;
+    });
+    return v;
+}
+
+hipError_t launch_step_vec(int lat, int dtype, int K, int kind, const void* src, void* dst, const VecGeom& geo,
+                           double omega, double theta, hipStream_t s)
+{
+    return by_pair(lat, dtype, [&](auto Lt, auto* Sp) {
+        using L = decltype(Lt);
+        using S = std::remove_pointer_t<decltype(Sp)>;
+        return launch_step_vec_l<L, S>(K, kind, src, dst, geo, omega, theta, s);
+    });
+}
+
+hipError_t launch_step_batch(int lat, int dtype, int K, int kind, const void* src, void* dst, const TileDesc* tiles,
+                             int ntiles, const BoxDesc* boxes, double theta, int block, int grid, hipStream_t s)
+{
+    return by_pair(lat, dtype, [&](auto Lt, auto* Sp) {
+        using L = decltype(Lt);
+        using S = std::remove_pointer_t<decltype(Sp)>;
+        return launch_step_batch_l<L, S>(K, kind, src, dst, tiles, ntiles, boxes, theta, block, grid, s);
+    });
+}
+
+// ---------------------------------------------------------------------------
 // Host copies of the descriptors.
 // ---------------------------------------------------------------------------
 
@@ -320,6 +376,7 @@ bool lattice_info(int lat, LatticeInfo* out)
 {
     switch (lat) {
     case kD2Q9: fill_info<D2Q9>(out); return true;
+    case kD3Q15: fill_info<D3Q15>(out); return true;
     case kD3Q19: fill_info<D3Q19>(out); return true;
     case kD3Q39: fill_info<D3Q39>(out); return true;
     default: return false;

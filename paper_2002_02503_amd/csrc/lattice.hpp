@@ -1,15 +1,16 @@
 // Lattice descriptors for the GPU path: velocity sets c_i, weights w_i and the
-// lattice temperature T0 of D2Q9, D3Q19 and D3Q39.
+// lattice temperature T0 of D2Q9, D3Q15, D3Q19 and D3Q39.
 //
 // A lattice is "2N-th order isotropic" when sum_i w_i c_i...c_i (n times)
 // equals T0^(n/2) times the n-th order Kronecker-delta tensor for even
 // n <= 2N and vanishes for odd n (eq. iso, section "Basic Filtered Collision
-// Formulation").  D2Q9 and D3Q19 have 2N = 4 with T0 = 1/3; D3Q39 has 2N = 6
-// with T0 = 2/3 (its six shell weights are the unique positive solution of
-// eq. iso through sixth order).
+// Formulation").  D2Q9, D3Q15 and D3Q19 have 2N = 4 with T0 = 1/3; D3Q39 has
+// 2N = 6 with T0 = 2/3 (its six shell weights are the unique positive
+// solution of eq. iso through sixth order).
 //
 // Weight quantum.  Every weight is an integer multiple of 1/S (S = 36 for
-// D2Q9 and D3Q19, 6480 for D3Q39), so W_i = S w_i are small integers, exact in
+// D2Q9 and D3Q19, 72 for D3Q15, 6480 for D3Q39), so W_i = S w_i are small
+// integers, exact in
 // any floating-point type.  The kernels keep the populations in these units
 // (see collide.hpp): no rounded weight ever enters the arithmetic.
 //
@@ -37,7 +38,12 @@
 
 namespace lbm {
 
-enum LatticeId : int { kD2Q9 = 0, kD3Q19 = 1, kD3Q39 = 2 };
+enum LatticeId : int { kD2Q9 = 0, kD3Q19 = 1, kD3Q39 = 2, kD3Q15 = 3 };
+
+// Collision operators of the step (collide.hpp): the filtered operator, BGK
+// with the same truncated equilibrium, and the filtered operator with the
+// energy-flux term of weight theta.
+enum CollisionKind : int { kFiltered = 0, kBGK = 1, kFilteredQ = 2 };
 
 struct D2Q9 {
     static constexpr int id = kD2Q9;
@@ -54,6 +60,25 @@ struct D2Q9 {
         4.0 / 9.0,
         1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
         1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+};
+
+struct D3Q15 {
+    static constexpr int id = kD3Q15;
+    static constexpr int D = 3, Q = 15, TWO_N = 4, K_DEFAULT = 3, K_MAX = 3;
+    static constexpr int R = 1;
+    static constexpr double T0 = 1.0 / 3.0, INV_T0 = 3.0;
+    static constexpr int S = 72;
+    static constexpr int W[Q] = {16, 8, 8, 8, 8, 8, 8, 1, 1, 1, 1, 1, 1, 1, 1};
+    static constexpr int8_t c[Q][3] = {
+        {0, 0, 0},
+        {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+        {1, 1, 1}, {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1},
+        {1, -1, 1}, {-1, 1, -1}, {-1, 1, 1}, {1, -1, -1}};
+    static constexpr double w[Q] = {
+        2.0 / 9.0,
+        1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+        1.0 / 72.0, 1.0 / 72.0, 1.0 / 72.0, 1.0 / 72.0,
+        1.0 / 72.0, 1.0 / 72.0, 1.0 / 72.0, 1.0 / 72.0};
 };
 
 struct D3Q19 {
@@ -137,9 +162,12 @@ constexpr bool opposite_pairs()
             if (L::c[k + 1][a] != -L::c[k][a] || L::W[k + 1] != L::W[k]) return false;
     return true;
 }
-static_assert(opposite_pairs<D2Q9>() && opposite_pairs<D3Q19>() && opposite_pairs<D3Q39>(), "pair order");
+static_assert(opposite_pairs<D2Q9>() && opposite_pairs<D3Q15>() && opposite_pairs<D3Q19>() &&
+                  opposite_pairs<D3Q39>(),
+              "pair order");
 
 static_assert(integer_weights_consistent<D2Q9>(), "D2Q9 weight quantum");
+static_assert(integer_weights_consistent<D3Q15>(), "D3Q15 weight quantum");
 static_assert(integer_weights_consistent<D3Q19>(), "D3Q19 weight quantum");
 static_assert(integer_weights_consistent<D3Q39>(), "D3Q39 weight quantum");
 
@@ -175,8 +203,8 @@ constexpr bool mem_order_is_permutation()
         if (mem_pop<L>(m) < 0 || mem_row<L>(mem_pop<L>(m)) != m) return false;
     return true;
 }
-static_assert(mem_order_is_permutation<D2Q9>() && mem_order_is_permutation<D3Q19>() &&
-                  mem_order_is_permutation<D3Q39>(),
+static_assert(mem_order_is_permutation<D2Q9>() && mem_order_is_permutation<D3Q15>() &&
+                  mem_order_is_permutation<D3Q19>() && mem_order_is_permutation<D3Q39>(),
               "tile row order");
 
 // Calls f(std::integral_constant<int, i>{}) for i = 0 .. N-1, fully unrolled.

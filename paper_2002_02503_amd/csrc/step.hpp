@@ -1,6 +1,11 @@
 // The fused pull-stream + collide step on a single box: one site per thread
-// (k_step) or V sites per lane (k_step_vec).
+// (k_step) or V sites per lane (k_step_vec), templated on lattice, storage
+// type, Hermite order and collision kind.  Included by the per-lattice
+// translation units, which instantiate the launchers for one lattice.
+#pragma once
+
 #include "device.hpp"
+#include "step_launch.hpp"
 
 namespace lbm {
 
@@ -12,9 +17,9 @@ namespace lbm {
 // 32-bit lane offset.
 // ---------------------------------------------------------------------------
 
-template <class L, class S, int K>
+template <class L, class S, int K, int KIND>
 __global__ __launch_bounds__(256) void k_step(const S* __restrict__ src, S* __restrict__ dst, StepGeom geo,
-                                              typename Store<S>::R omega)
+                                              typename Store<S>::R omega, typename Store<S>::R theta)
 {
     using ST = Store<S>;
     using R = typename ST::R;
@@ -45,7 +50,7 @@ __global__ __launch_bounds__(256) void k_step(const S* __restrict__ src, S* __re
         g[i] = load_population<ST, cx>(at32(p, unsigned(xw[RR - cx])));
     });
 
-    collide_site<L, K, PROJ, R>(g, omega);
+    collide_site<L, K, KIND, PROJ, R>(g, omega, theta);
 
     S* q = dst + (long long)(z * geo.ny + y) * tile;
     unroll<L::Q>([&](auto M) {
@@ -54,9 +59,9 @@ __global__ __launch_bounds__(256) void k_step(const S* __restrict__ src, S* __re
     });
 }
 
-template <class L, class S, int K>
+template <class L, class S, int K, int KIND>
 __global__ __launch_bounds__(256) void k_step_vec(const S* __restrict__ src, S* __restrict__ dst, VecGeom geo,
-                                                  typename Store<S>::R omega)
+                                                  typename Store<S>::R omega, typename Store<S>::R theta)
 {
     using R = typename Store<S>::R;
     constexpr int V = vec_sites<S>();
@@ -114,7 +119,7 @@ __global__ __launch_bounds__(256) void k_step_vec(const S* __restrict__ src, S* 
 
     unroll<V>([&](auto J) {
         constexpr int j = decltype(J)::value;
-        collide_site<L, K, PROJ, R>(g[j], omega);
+        collide_site<L, K, KIND, PROJ, R>(g[j], omega, theta);
     });
 
     S* q = dst + (long long)row * tile + (long long)li * V;
@@ -130,51 +135,44 @@ __global__ __launch_bounds__(256) void k_step_vec(const S* __restrict__ src, S* 
     });
 }
 
-hipError_t launch_step(int lat, int dtype, int K, const void* src, void* dst, const StepGeom& geo, double omega,
-                       int block, hipStream_t s)
+template <class L, class S>
+hipError_t launch_step_l(int K, int kind, const void* src, void* dst, const StepGeom& geo, double omega,
+                         double theta, int block, hipStream_t s)
 {
-    return dispatch(lat, dtype, K, [&](auto Lt, auto* Sp, auto Kc) -> hipError_t {
-        using L = decltype(Lt);
-        using S = std::remove_pointer_t<decltype(Sp)>;
+    return dispatch_pair<L, S>(K, kind, [&](auto, auto*, auto Kc, auto Kind) -> hipError_t {
         using R = typename Store<S>::R;
         constexpr int KK = decltype(Kc)::value;
-        k_step<L, S, KK><<<dim3(unsigned(geo.xblocks), unsigned(geo.ny), unsigned(geo.nz)), block, 0, s>>>(
-            static_cast<const S*>(src), static_cast<S*>(dst), geo, R(omega));
+        constexpr int KD = decltype(Kind)::value;
+        k_step<L, S, KK, KD><<<dim3(unsigned(geo.xblocks), unsigned(geo.ny), unsigned(geo.nz)), block, 0, s>>>(
+            static_cast<const S*>(src), static_cast<S*>(dst), geo, R(omega), R(theta));
         return hipGetLastError();
     });
 }
 
-int vec_sites_per_lane(int lat, int dtype)
+template <class L, class S>
+int vec_sites_l()
 {
-    int v = 0;
-    (void)dispatch(lat, dtype, 2, [&](auto Lt, auto* Sp, auto) -> hipError_t {
-        using L = decltype(Lt);
-        using S = std::remove_pointer_t<decltype(Sp)>;
-        constexpr int V = vec_sites<S>();
-        v = (L::R < V) ? V : 0;
-        return hipSuccess;
-    });
-    return v;
+    return (L::R < vec_sites<S>()) ? vec_sites<S>() : 0;
 }
 
-hipError_t launch_step_vec(int lat, int dtype, int K, const void* src, void* dst, const VecGeom& geo, double omega,
-                           hipStream_t s)
+template <class L, class S>
+hipError_t launch_step_vec_l(int K, int kind, const void* src, void* dst, const VecGeom& geo, double omega,
+                             double theta, hipStream_t s)
 {
-    return dispatch(lat, dtype, K, [&](auto Lt, auto* Sp, auto Kc) -> hipError_t {
-        using L = decltype(Lt);
-        using S = std::remove_pointer_t<decltype(Sp)>;
-        using R = typename Store<S>::R;
-        constexpr int KK = decltype(Kc)::value;
-        if constexpr (L::R < vec_sites<S>()) {
+    if constexpr (L::R < vec_sites<S>()) {
+        return dispatch_pair<L, S>(K, kind, [&](auto, auto*, auto Kc, auto Kind) -> hipError_t {
+            using R = typename Store<S>::R;
+            constexpr int KK = decltype(Kc)::value;
+            constexpr int KD = decltype(Kind)::value;
             const long long waves = (geo.nrows + geo.rows_per_wave - 1) / geo.rows_per_wave;
             const long long nblocks = (waves + 3) / 4;
-            k_step_vec<L, S, KK><<<dim3((unsigned)nblocks), 256, 0, s>>>(static_cast<const S*>(src),
-                                                                       static_cast<S*>(dst), geo, R(omega));
+            k_step_vec<L, S, KK, KD><<<dim3((unsigned)nblocks), 256, 0, s>>>(
+                static_cast<const S*>(src), static_cast<S*>(dst), geo, R(omega), R(theta));
             return hipGetLastError();
-        } else {
-            return hipErrorInvalidValue;
-        }
-    });
+        });
+    } else {
+        return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace lbm

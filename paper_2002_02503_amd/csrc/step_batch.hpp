@@ -1,5 +1,10 @@
-// The fused pull-stream + collide step on a batch of boxes.
+// The fused pull-stream + collide step on a batch of boxes, templated on
+// lattice, storage type, Hermite order and collision kind.  Included by the
+// per-lattice translation units.
+#pragma once
+
 #include "device.hpp"
+#include "step_launch.hpp"
 
 namespace lbm {
 
@@ -12,10 +17,10 @@ namespace lbm {
 // inside a box fit 32 bits (checked on the host).
 // ---------------------------------------------------------------------------
 
-template <class L, class S, int K>
+template <class L, class S, int K, int KIND>
 __global__ __launch_bounds__(256) void k_step_batch(const S* __restrict__ src, S* __restrict__ dst,
                                                     const TileDesc* __restrict__ tiles, int ntiles,
-                                                    const BoxDesc* __restrict__ boxes)
+                                                    const BoxDesc* __restrict__ boxes, typename Store<S>::R theta)
 {
     using ST = Store<S>;
     using R = typename ST::R;
@@ -66,7 +71,7 @@ __global__ __launch_bounds__(256) void k_step_batch(const S* __restrict__ src, S
             g[i] = load_population<ST, cx>(at32(sb, unsigned(off)));
         });
 
-        collide_site<L, K, PROJ, R>(g, R(b.omega));
+        collide_site<L, K, KIND, PROJ, R>(g, R(b.omega), theta);
 
         const int out_off = (z * b.ny + y) * tq + x;
         unroll<L::Q>([&](auto M) {
@@ -76,16 +81,17 @@ __global__ __launch_bounds__(256) void k_step_batch(const S* __restrict__ src, S
     }
 }
 
-hipError_t launch_step_batch(int lat, int dtype, int K, const void* src, void* dst, const TileDesc* tiles,
-                             int ntiles, const BoxDesc* boxes, int block, int grid, hipStream_t s)
+template <class L, class S>
+hipError_t launch_step_batch_l(int K, int kind, const void* src, void* dst, const TileDesc* tiles, int ntiles,
+                               const BoxDesc* boxes, double theta, int block, int grid, hipStream_t s)
 {
-    return dispatch(lat, dtype, K, [&](auto Lt, auto* Sp, auto Kc) -> hipError_t {
-        using L = decltype(Lt);
-        using S = std::remove_pointer_t<decltype(Sp)>;
+    return dispatch_pair<L, S>(K, kind, [&](auto, auto*, auto Kc, auto Kind) -> hipError_t {
+        using R = typename Store<S>::R;
         constexpr int KK = decltype(Kc)::value;
+        constexpr int KD = decltype(Kind)::value;
         const int g = (grid > 0 && grid < ntiles) ? grid : ntiles;
-        k_step_batch<L, S, KK><<<g, block, 0, s>>>(static_cast<const S*>(src), static_cast<S*>(dst), tiles, ntiles,
-                                                   boxes);
+        k_step_batch<L, S, KK, KD><<<g, block, 0, s>>>(static_cast<const S*>(src), static_cast<S*>(dst), tiles,
+                                                       ntiles, boxes, R(theta));
         return hipGetLastError();
     });
 }

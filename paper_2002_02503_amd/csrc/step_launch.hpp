@@ -1,0 +1,60 @@
+// Launchers of the fused step kernels for one (lattice, storage type).  Each
+// pair's instances are compiled in translation units of their own, which the
+// build writes (two lines each: include step.hpp or step_batch.hpp, then
+// LBM_DECLARE_*_INSTANCES for the pair); the runtime-lattice entry points in
+// internal.hpp forward to these.
+#pragma once
+
+#include "internal.hpp"
+#include "lattice.hpp"
+
+namespace lbm {
+
+struct bf16_t;
+
+// Single box, one site per thread: grid (xblocks, ny, nz) of `block` threads.
+template <class L, class S>
+hipError_t launch_step_l(int K, int kind, const void* src, void* dst, const StepGeom& geo, double omega,
+                         double theta, int block, hipStream_t s);
+
+// Sites per lane of the row-wave form (0: none for this pair).
+template <class L, class S>
+int vec_sites_l();
+
+// Single box, row-wave form.
+template <class L, class S>
+hipError_t launch_step_vec_l(int K, int kind, const void* src, void* dst, const VecGeom& geo, double omega,
+                             double theta, hipStream_t s);
+
+// Batch of boxes: a fixed grid walks the tile table.
+template <class L, class S>
+hipError_t launch_step_batch_l(int K, int kind, const void* src, void* dst, const TileDesc* tiles, int ntiles,
+                               const BoxDesc* boxes, double theta, int block, int grid, hipStream_t s);
+
+#define LBM_DECLARE_STEP_INSTANCES(EXT, L, S)                                                                    \
+    EXT template hipError_t launch_step_l<L, S>(int, int, const void*, void*, const StepGeom&, double, double,  \
+                                                int, hipStream_t);                                             \
+    EXT template int vec_sites_l<L, S>();                                                                      \
+    EXT template hipError_t launch_step_vec_l<L, S>(int, int, const void*, void*, const VecGeom&, double,      \
+                                                    double, hipStream_t);
+
+#define LBM_DECLARE_BATCH_INSTANCES(EXT, L, S)                                                                 \
+    EXT template hipError_t launch_step_batch_l<L, S>(int, int, const void*, void*, const TileDesc*, int,    \
+                                                      const BoxDesc*, double, int, int, hipStream_t);
+
+#define LBM_EXTERN_PAIR(L, S)                  \
+    LBM_DECLARE_STEP_INSTANCES(extern, L, S)   \
+    LBM_DECLARE_BATCH_INSTANCES(extern, L, S)
+
+#define LBM_EXTERN_LATTICE(L)       \
+    LBM_EXTERN_PAIR(L, double)      \
+    LBM_EXTERN_PAIR(L, float)       \
+    LBM_EXTERN_PAIR(L, _Float16)    \
+    LBM_EXTERN_PAIR(L, bf16_t)
+
+LBM_EXTERN_LATTICE(D2Q9)
+LBM_EXTERN_LATTICE(D3Q15)
+LBM_EXTERN_LATTICE(D3Q19)
+LBM_EXTERN_LATTICE(D3Q39)
+
+}  // namespace lbm

@@ -16,15 +16,17 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
-LATTICES = {"D2Q9": 0, "D3Q19": 1, "D3Q39": 2}
+LATTICES = {"D2Q9": 0, "D3Q19": 1, "D3Q39": 2, "D3Q15": 3}
 DTYPES = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
 DTYPE_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2}
 KERNELS = {"auto": 0, "scalar": 1, "row_wave": 2}
+COLLISIONS = {"filtered": 0, "bgk": 1}
 STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE", -4: "LBM_ENODEV",
           -5: "LBM_ESTATE", -6: "LBM_ENUMERIC"}
 
 # Every entry point declared in include/lbm.h.
-EXPORTS = ["lbm_create", "lbm_create_batch", "lbm_set_hermite_order", "lbm_set_stream", "lbm_state_bytes",
+EXPORTS = ["lbm_create", "lbm_create_batch", "lbm_set_hermite_order", "lbm_set_collision", "lbm_set_stream",
+           "lbm_state_bytes",
            "lbm_bind_state", "lbm_init", "lbm_step", "lbm_prepare", "lbm_set_graph_chunk", "lbm_set_launch",
            "lbm_set_kernel", "lbm_tune", "lbm_moments", "lbm_totals", "lbm_residual", "lbm_checkpoint_bytes", "lbm_get_state",
            "lbm_set_state", "lbm_get_info", "lbm_sync", "lbm_destroy", "lbm_last_error", "lbm_lattice_table",
@@ -44,7 +46,8 @@ class lbm_info(ctypes.Structure):
                 ("T0", ctypes.c_double), ("nbox", ctypes.c_int32), ("dims", ctypes.c_int64 * 3),
                 ("nsites", ctypes.c_int64), ("t", ctypes.c_int64), ("bytes_per_site_update", ctypes.c_int64),
                 ("state_bytes", ctypes.c_uint64), ("block", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("graph_chunk", ctypes.c_int32), ("kernel", ctypes.c_int32)]
+                ("graph_chunk", ctypes.c_int32), ("kernel", ctypes.c_int32), ("collision", ctypes.c_int32),
+                ("theta", ctypes.c_double)]
 
 
 _lib = None
@@ -75,6 +78,7 @@ def load_library() -> ctypes.CDLL:
         "lbm_create": [ctypes.POINTER(vp), ctypes.c_int32, i64p, ctypes.c_double, ctypes.c_int32],
         "lbm_create_batch": [ctypes.POINTER(vp), ctypes.c_int32, ctypes.c_int32, i64p, dp, ctypes.c_int32],
         "lbm_set_hermite_order": [vp, ctypes.c_int32],
+        "lbm_set_collision": [vp, ctypes.c_int32, ctypes.c_double],
         "lbm_set_stream": [vp, vp],
         "lbm_state_bytes": [vp, ctypes.POINTER(ctypes.c_size_t)],
         "lbm_bind_state": [vp, vp, vp, ctypes.c_size_t],
@@ -167,12 +171,14 @@ class Simulation:
     Parameters follow lbm_create / lbm_create_batch: lattice name, dims
     (nx, ny, nz) or a list of them for a batch, tau (one value or one per
     box), storage dtype ("fp64", "fp32", "fp16", "bf16"), optional Hermite
-    order K, launch shape (block, grid) and steps per captured graph.
+    order K, collision operator ("filtered" or "bgk") with the energy-flux
+    weight theta (lbm_set_collision), launch shape (block, grid) and steps per
+    captured graph.
     """
 
     def __init__(self, lattice: str, dims, tau, dtype: str = "fp32", K: int | None = None,
                  block: int = 0, grid: int = 0, graph_chunk: int | None = None, torch_memory: bool = True,
-                 stream=None, kernel: str = "auto"):
+                 stream=None, kernel: str = "auto", collision: str = "filtered", theta: float = 0.0):
         self.lib = load_library()
         self.lattice = lattice
         self.dtype = dtype
@@ -195,6 +201,8 @@ class Simulation:
         try:
             if K is not None:
                 _check(self.lib.lbm_set_hermite_order(self.h, int(K)))
+            if collision != "filtered" or theta != 0.0:
+                _check(self.lib.lbm_set_collision(self.h, COLLISIONS[collision], float(theta)))
             if block or grid:
                 _check(self.lib.lbm_set_launch(self.h, int(block), int(grid)))
             if graph_chunk is not None:

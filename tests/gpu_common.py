@@ -34,8 +34,8 @@ def run_gpu(lattice, dims, tau, dtype, rho, u, steps, K=None, **kw):
         return sim.moments()
 
 
-def run_oracle(lattice, dims, tau, rho, u, steps, K=None, mode="literal"):
-    sim = oracle.Sim(lattice, dims, tau, K=K, mode=mode).init(rho, u)
+def run_oracle(lattice, dims, tau, rho, u, steps, K=None, mode="literal", **kw):
+    sim = oracle.Sim(lattice, dims, tau, K=K, mode=mode, **kw).init(rho, u)
     sim.step(steps)
     return sim.moments()
 

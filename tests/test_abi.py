@@ -44,7 +44,7 @@ def test_every_declared_symbol_is_exported(lib):
     assert sorted(lbm.EXPORTS) == declared
 
 
-@pytest.mark.parametrize("name", ["D2Q9", "D3Q19", "D3Q39"])
+@pytest.mark.parametrize("name", ["D2Q9", "D3Q15", "D3Q19", "D3Q39"])
 def test_library_lattice_matches_oracle(lib, oracle_mod, name):
     """Same velocity set (as a set of (c, w) pairs), T0 and 2N as the oracle's
     independently typed tables."""

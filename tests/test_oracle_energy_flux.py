@@ -17,6 +17,7 @@ expansion against what the paper and the mathematics fix:
     relaxed by (1 - 1/tau) theta;
   * physics: the shear viscosity T0 (tau - 1/2) does not depend on theta.
 """
+import itertools
 import math
 
 import numpy as np
@@ -226,3 +227,37 @@ def test_shear_viscosity_does_not_depend_on_theta(oracle_mod, name):
         assert abs(g1 / (T0 * (tau - 0.5) * k * k) - 1) < 6e-3
         d[n] = g1 / g0 - 1
     assert 3.8 < d[32] / d[64] < 4.2, d
+
+
+def test_d3q19_stability_bound_of_the_energy_flux_term(oracle_mod):
+    """On D3Q19 the third-order Hermite tensors are not orthogonal under the
+    lattice weights (the (3,3) pair fails), so the term maps the mixed
+    components (Q_xxy, Q_yzz) through a matrix with eigenvalues 1/2 and 3/2
+    (the lattice's sixth moments), and the post-collision energy flux of that
+    mode is (1 - 1/tau) theta 3/2 times the incoming one.  The run is therefore
+    stable only while |1 - 1/tau| theta 3/2 < 1: at tau = 0.55, theta = 0.5
+    stays bounded and theta = 1 grows without bound."""
+    L = oracle_mod.lattice("D3Q19")
+    c = L["c"].astype(float)
+    M = np.zeros((2, 2))
+    for j, a in enumerate([(0, 0, 1), (1, 2, 2)]):  # Q_xxy, Q_yzz
+        Q = np.zeros((3, 3, 3))
+        for p in itertools.permutations(a):
+            Q[p] = 1.0
+        f = oracle_mod.fq("D3Q19", 3, np.zeros(3), Q)
+        T = np.einsum("ia,ib,ig,i->abg", c, c, c, f)
+        M[0, j], M[1, j] = T[0, 0, 1], T[1, 2, 2]
+    assert np.allclose(sorted(np.linalg.eigvalsh(M)), [0.5, 1.5], atol=1e-14)
+    n, tau = 64, 0.55
+    x = np.arange(n)
+    u = np.zeros((3, 1, 1, n))
+    u[1, 0, 0] = 0.01 * np.sin(2 * np.pi * x / n)
+    amp = {}
+    for theta in [0.5, 1.0]:
+        sim = oracle_mod.Sim("D3Q19", (n, 1, 1), tau, theta=theta, mode="closed").init(np.ones((1, 1, n)), u)
+        with np.errstate(all="ignore"):
+            sim.step(200)
+            _, uu = sim.moments()
+        amp[theta] = float(np.abs(uu[1]).max())
+    assert amp[0.5] < 0.01
+    assert not (amp[1.0] < 1.0)  # grown past any physical value (or overflowed)
