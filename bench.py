@@ -67,7 +67,8 @@ def timed_steps(sim, steps: int, warmup: int) -> float:
     return e0.elapsed_time(e1) / steps
 
 
-KERNEL_NAMES = {1: "scalar", 2: "row_wave"}
+KERNEL_NAMES = {1: "scalar", 2: "row_wave", 3: "in_place"}
+KERNEL_SYMBOLS = {"scalar": "k_step", "row_wave": "k_step_vec", "in_place": "k_step_ip"}
 
 
 def measure_box(lattice, dims, tau, dtype, rho, u, steps, warmup, tune=True, **kw):
@@ -170,7 +171,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle leg (CPU baseline timing and error statements)")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle stepping")
-    ap.add_argument("--kernel", choices=["tune", "scalar", "row_wave"], default="tune",
+    ap.add_argument("--kernel", choices=["tune", "scalar", "row_wave", "in_place"], default="tune",
                     help="headline step kernel: autotuned (default) or pinned")
     ap.add_argument("--block", type=int, default=256, help="threads per block when --kernel is pinned")
     args = ap.parse_args()
@@ -194,7 +195,7 @@ def main():
     if args.kernel == "tune":
         head = measure_box("D3Q19", (256, 256, 256), tau, "fp32", rho, u, args.steps, args.warmup)
     else:
-        pin = {"kernel": args.kernel, "block": args.block if args.kernel == "scalar" else 0}
+        pin = {"kernel": args.kernel, "block": args.block if args.kernel != "row_wave" else 0}
         head = measure_box("D3Q19", (256, 256, 256), tau, "fp32", rho, u, args.steps, args.warmup, tune=False, **pin)
     log(f"headline: {head['value']:.0f} MLUPS with the {head['kernel']} step, block {head['block']}")
     nsites = head["nsites"]
@@ -202,7 +203,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": head["achieved_GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": head["achieved_GBs"] / PEAK_HBM_GBS, "traffic": traffic,
                 "algorithmic_bytes_per_launch": head["bytes_per_site_update"] * nsites,
-                "kernel": ("k_step" if head["kernel"] == "scalar" else "k_step_vec") + "<D3Q19, float, K=3>",
+                "kernel": KERNEL_SYMBOLS[head["kernel"]] + "<D3Q19, float, K=3>",
                 "launch": {"kernel": head["kernel"], "block": head["block"]}, "traffic_source": traffic_src}
 
     log("copy probe at the same footprint")
@@ -228,7 +229,19 @@ def main():
         srho, su = inputs.shear_wave((192, 192, 192), 0.01, (0.2, 0.0, 0.0))
         variants["d3q39_fp32_192"] = measure_box("D3Q39", (192, 192, 192), 0.6, "fp32", srho, su, 1000,
                                                  args.warmup)
+        log("D3Q39 192^3 FP32 at K = 5, 300 steps")
+        variants["d3q39_k5_fp32_192"] = measure_box("D3Q39", (192, 192, 192), 0.6, "fp32", srho, su, 300,
+                                                    args.warmup, K=5)
         del srho, su
+        # the other collision kinds and lattices on the headline workload
+        log("BGK and the energy-flux kind on the 256^3 FP32 turbulence box, 300 steps each")
+        variants["d3q19_bgk_fp32_256"] = measure_box("D3Q19", (256, 256, 256), tau, "fp32", rho, u, 300,
+                                                     args.warmup, collision="bgk")
+        # theta inside D3Q19's bound |1 - 1/tau| theta 3/2 < 1 at tau = 0.51
+        variants["d3q19_theta0.5_fp32_256"] = measure_box("D3Q19", (256, 256, 256), tau, "fp32", rho, u, 300,
+                                                          args.warmup, theta=0.5)
+        log("D3Q15 on the 256^3 turbulence box, FP32, 300 steps")
+        variants["d3q15_fp32_256"] = measure_box("D3Q15", (256, 256, 256), tau, "fp32", rho, u, 300, args.warmup)
 
     cpu, errors = None, {}
     if not args.no_cpu_baseline:

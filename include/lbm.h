@@ -71,7 +71,10 @@ typedef enum {
 typedef enum {
     LBM_KERNEL_AUTO = 0,      /* the scalar step unless a tuned choice was set */
     LBM_KERNEL_SCALAR = 1,    /* one site per thread, 4/8-byte accesses */
-    LBM_KERNEL_ROW_WAVE = 2   /* V sites per lane, 8/16-byte accesses, x-neighbours by lane shuffle */
+    LBM_KERNEL_ROW_WAVE = 2,  /* V sites per lane, 8/16-byte accesses, x-neighbours by lane shuffle */
+    LBM_KERNEL_IN_PLACE = 3   /* one site per thread on one buffer: each step reads and writes the same
+                                 elements, alternating between two layouts of the state (bit-identical
+                                 results; readers see the natural layout) */
 } lbm_kernel;
 
 typedef struct {
@@ -168,18 +171,23 @@ lbm_status lbm_set_graph_chunk(lbm_t h, int32_t steps);
  * block per tile).  Only before lbm_init. */
 lbm_status lbm_set_launch(lbm_t h, int32_t block, int32_t grid);
 
-/* Choose the single-box step kernel.  Both variants compute the same bits.
+/* Choose the single-box step kernel.  All variants compute the same bits.
  * LBM_KERNEL_ROW_WAVE needs nx to be a multiple of the sites per lane V (4 for
  * FP32/FP16/BF16, 2 for FP64) with nx / V <= 64, and V above the largest
- * velocity component (so FP64 D3Q39 has none); else LBM_EINVAL.  Batches
- * always use the tiled batched kernel.  Only before lbm_init. */
+ * velocity component (so FP64 D3Q39 has none); else LBM_EINVAL.
+ * LBM_KERNEL_IN_PLACE steps the state inside one of the two buffers; on odd
+ * step counts the state is kept in a swapped layout, and every call that reads
+ * it (moments, totals, residual, checkpoint) first rewrites it into the
+ * natural layout in the other buffer.  Batches always use the tiled batched
+ * kernel.  Only before lbm_init. */
 lbm_status lbm_set_kernel(lbm_t h, int32_t kernel);
 
 /* Autotune the step's launch: time every candidate (single box: the scalar
- * step at 64/128/256 threads per block and the row-wave step where it
- * applies; batch: 64/128/256 threads x grids of one block per tile or
- * 1024/2048/4096 persistent blocks) over `steps` steps with HIP events, in
- * three interleaved rounds, and keep the candidate with the fastest round.  The state is saved before and restored after, so t and
+ * step at 64/128/256 threads per block, the in-place step at 256, and the
+ * row-wave step where it applies; batch: 64/128/256 threads x grids of one
+ * block per tile or 1024/2048/4096 persistent blocks) over `steps` steps with
+ * HIP events, in three interleaved rounds, and keep the candidate with the
+ * fastest round.  The state is saved before and restored after, so t and
  * the populations are unchanged (all candidates compute the same bits).
  * Choices are appended to the text file `cache_path` (NULL: the path in the
  * environment variable LBM_TUNE_CACHE, or no cache); a later call with the same

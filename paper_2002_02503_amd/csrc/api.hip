@@ -221,13 +221,32 @@ lbm_status build_tiles(lbm_ctx* h, int block)
     std::vector<TileDesc> tiles;
     for (int b = 0; b < h->nbox; ++b) {
         const int nx = int(h->dims[3 * b]), ny = int(h->dims[3 * b + 1]), nz = int(h->dims[3 * b + 2]);
+        TileDesc t{};
+        t.nx = nx;
+        t.ny = ny;
+        t.nz = nz;
+        t.inv_nx = float(1.0 / double(nx));
+        t.offset = h->offset[b];
+        t.omega = 1.0 - 1.0 / h->tau[b];
+        t.box = b;
         for (int z = 0; z < nz; ++z) {
+            t.z = z;
             if (nx <= block) {
                 const int per = block / nx;  // whole rows per tile
-                for (int y = 0; y < ny; y += per) tiles.push_back({b, z, y, (ny - y < per) ? ny - y : per, 0});
+                for (int y = 0; y < ny; y += per) {
+                    t.y0 = y;
+                    t.rows = (ny - y < per) ? ny - y : per;
+                    t.x0 = 0;
+                    tiles.push_back(t);
+                }
             } else {
                 for (int y = 0; y < ny; ++y)
-                    for (int x0 = 0; x0 < nx; x0 += block) tiles.push_back({b, z, y, 1, x0});
+                    for (int x0 = 0; x0 < nx; x0 += block) {
+                        t.y0 = y;
+                        t.rows = 1;
+                        t.x0 = x0;
+                        tiles.push_back(t);
+                    }
             }
         }
     }
@@ -366,12 +385,30 @@ lbm_status ensure_buffers(lbm_ctx* h)
     return LBM_OK;
 }
 
-// One step from buf[src_idx] into buf[src_idx ^ 1] on stream s.
-hipError_t launch_one(lbm_ctx* h, int src_idx, hipStream_t s)
+bool in_place(const lbm_ctx* h) { return is_single(h) && effective_kernel(h) == LBM_KERNEL_IN_PLACE; }
+
+StepGeom single_geom(const lbm_ctx* h, int block)
 {
-    const void* src = h->buf[src_idx];
-    void* dst = h->buf[src_idx ^ 1];
+    StepGeom geo;
+    geo.nx = int(h->dims[0]);
+    geo.ny = int(h->dims[1]);
+    geo.nz = int(h->dims[2]);
+    geo.xblocks = (geo.nx + block - 1) / block;
+    return geo;
+}
+
+// One step on stream s.  Two-buffer kernels step from buf[parity] into
+// buf[parity ^ 1].  The in-place kernel steps buf[0] from the natural layout
+// (parity 0) to the swapped one, or back (parity 1).  Either way the next
+// step has parity ^ 1, which h->cur tracks.
+hipError_t launch_one(lbm_ctx* h, int parity, hipStream_t s)
+{
     const int block = effective_block(h);
+    if (in_place(h))
+        return launch_step_ip(h->lattice, h->dtype, h->K, step_kind(h), h->buf[0], parity == 0, single_geom(h, block),
+                              1.0 - 1.0 / h->tau[0], h->theta, block, s);
+    const void* src = h->buf[parity];
+    void* dst = h->buf[parity ^ 1];
     if (is_single(h) && effective_kernel(h) == LBM_KERNEL_ROW_WAVE) {
         VecGeom geo;
         const int V = row_wave_sites(h);
@@ -384,17 +421,47 @@ hipError_t launch_one(lbm_ctx* h, int src_idx, hipStream_t s)
         return launch_step_vec(h->lattice, h->dtype, h->K, step_kind(h), src, dst, geo, 1.0 - 1.0 / h->tau[0],
                                h->theta, s);
     }
-    if (is_single(h)) {
-        StepGeom geo;
-        geo.nx = int(h->dims[0]);
-        geo.ny = int(h->dims[1]);
-        geo.nz = int(h->dims[2]);
-        geo.xblocks = (geo.nx + block - 1) / block;
-        return launch_step(h->lattice, h->dtype, h->K, step_kind(h), src, dst, geo, 1.0 - 1.0 / h->tau[0],
-                           h->theta, block, s);
+    if (is_single(h))
+        return launch_step(h->lattice, h->dtype, h->K, step_kind(h), src, dst, single_geom(h, block),
+                           1.0 - 1.0 / h->tau[0], h->theta, block, s);
+    return launch_step_batch(h->lattice, h->dtype, h->K, step_kind(h), src, dst, h->d_tiles, h->ntiles, h->theta,
+                             block, h->grid, s);
+}
+
+// The current state in the natural layout, for the calls that read it: the
+// buffer that holds it, or, when the in-place step left it swapped, the other
+// buffer after the swap is undone into it (the state itself stays put).
+lbm_status natural_state(lbm_ctx* h, const void** out)
+{
+    if (!in_place(h)) {
+        *out = h->buf[h->cur];
+        return LBM_OK;
     }
-    return launch_step_batch(h->lattice, h->dtype, h->K, step_kind(h), src, dst, h->d_tiles, h->ntiles,
-                             h->d_boxes, h->theta, block, h->grid, s);
+    if (h->cur == 0) {
+        *out = h->buf[0];
+        return LBM_OK;
+    }
+    const int block = effective_block(h);
+    hipError_t e = launch_unswap(h->lattice, h->dtype, h->buf[0], h->buf[1], single_geom(h, block), block, h->stream);
+    if (e != hipSuccess) return fail_hip(e, "unswap kernel");
+    *out = h->buf[1];
+    return LBM_OK;
+}
+
+// Bring the state into buf[0] in the natural layout (cur = 0), valid for
+// every step kernel, before the kernel choice changes on an initialised
+// handle.  Swaps the two buffer pointers where that suffices.
+lbm_status canonicalize(lbm_ctx* h)
+{
+    if (!h->initialized || h->cur == 0) return LBM_OK;
+    if (in_place(h)) {
+        const void* nat = nullptr;
+        if (lbm_status st = natural_state(h, &nat)) return st;
+    }
+    std::swap(h->buf[0], h->buf[1]);
+    h->cur = 0;
+    drop_graphs(h);
+    return LBM_OK;
 }
 
 lbm_status build_graph(lbm_ctx* h, int parity)
@@ -544,8 +611,11 @@ lbm_status lbm_set_launch(lbm_t h, int32_t block, int32_t grid)
 lbm_status lbm_set_kernel(lbm_t h, int32_t kernel)
 {
     if (lbm_status st = check_handle(h)) return st;
-    if (kernel != LBM_KERNEL_AUTO && kernel != LBM_KERNEL_SCALAR && kernel != LBM_KERNEL_ROW_WAVE)
+    if (kernel != LBM_KERNEL_AUTO && kernel != LBM_KERNEL_SCALAR && kernel != LBM_KERNEL_ROW_WAVE &&
+        kernel != LBM_KERNEL_IN_PLACE)
         return fail(LBM_EINVAL, "unknown kernel variant %d", kernel);
+    if (kernel == LBM_KERNEL_IN_PLACE && !is_single(h))
+        return fail(LBM_EINVAL, "the in-place step is for a single box; batches use the tiled batched kernel");
     if (kernel == LBM_KERNEL_ROW_WAVE && !row_wave_sites(h))
         return fail(LBM_EINVAL, "the row-wave step needs a single box with nx a multiple of the sites per lane "
                                 "and at most 64 lanes per row");
@@ -663,12 +733,16 @@ void cache_store(const char* path, const std::string& key, const LaunchChoice& c
     out << key << " | " << c.kernel << " " << c.block << " " << c.grid << "\n";
 }
 
-void apply_choice(lbm_ctx* h, const LaunchChoice& c)
+// Switch the launch; the state is first brought into the natural layout in
+// buf[0], the one place every kernel can start from.
+lbm_status apply_choice(lbm_ctx* h, const LaunchChoice& c)
 {
+    if (lbm_status st = canonicalize(h)) return st;
     h->kernel = c.kernel;
     h->block = c.block;
     h->grid = c.grid;
     drop_graphs(h);
+    return LBM_OK;
 }
 
 }  // namespace
@@ -685,21 +759,24 @@ lbm_status lbm_tune(lbm_t h, int32_t steps, const char* cache_path)
     LaunchChoice best;
     if (cache_lookup(cache_path, key, &best)) {
         if (best.kernel == LBM_KERNEL_ROW_WAVE && !row_wave_sites(h)) best.kernel = LBM_KERNEL_SCALAR;
-        apply_choice(h, best);
-        return LBM_OK;
+        if (best.kernel == LBM_KERNEL_IN_PLACE && !is_single(h)) best.kernel = LBM_KERNEL_SCALAR;
+        return apply_choice(h, best);
     }
     HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
 
     std::vector<LaunchChoice> cand;
     if (is_single(h)) {
         for (int b : {64, 128, 256}) cand.push_back({LBM_KERNEL_SCALAR, b, 0});
+        cand.push_back({LBM_KERNEL_IN_PLACE, 256, 0});
         if (row_wave_sites(h)) cand.push_back({LBM_KERNEL_ROW_WAVE, 0, 0});
     } else {
         for (int b : {64, 128, 256})
             for (int g : {0, 1024, 2048, 4096}) cand.push_back({LBM_KERNEL_SCALAR, b, g});
     }
 
-    // tuning steps the state: keep a copy and restore it afterwards
+    // tuning steps the state: keep a copy and restore it afterwards; the
+    // candidates switch kernels, so start from the natural layout in buf[0]
+    if (lbm_status st = canonicalize(h)) return st;
     const int cur0 = h->cur;
     const int64_t t0 = h->t;
     const LaunchChoice old = {h->kernel, h->block, h->grid};
@@ -716,7 +793,7 @@ lbm_status lbm_tune(lbm_t h, int32_t steps, const char* cache_path)
     std::vector<float> cand_ms(cand.size(), 0.f);
     for (int round = 0; round < kTuneRounds && st == LBM_OK; ++round) {
         for (size_t k = 0; k < cand.size() && st == LBM_OK; ++k) {
-            apply_choice(h, cand[k]);
+            if ((st = apply_choice(h, cand[k])) != LBM_OK) break;
             if ((st = lbm_step(h, 2)) != LBM_OK) break;
             if ((e = hipEventRecord(e0, h->stream)) != hipSuccess) { st = fail_hip(e, "hipEventRecord"); break; }
             if ((st = lbm_step(h, steps)) != LBM_OK) break;
@@ -742,11 +819,11 @@ lbm_status lbm_tune(lbm_t h, int32_t steps, const char* cache_path)
     h->cur = cur0;
     h->t = t0;
     if (st != LBM_OK) {
-        apply_choice(h, old);
+        (void)apply_choice(h, old);
         return st;
     }
     if (re != hipSuccess) return fail_hip(re, "restoring the state after tuning");
-    apply_choice(h, best);
+    if (lbm_status ast = apply_choice(h, best)) return ast;
     cache_store(cache_path, key, best);
     return LBM_OK;
 }
@@ -764,7 +841,12 @@ lbm_status lbm_moments(lbm_t h, double* rho, double* u, int32_t on_device)
         HIP_TRY(hipMalloc(&drho, n * (1 + D) * sizeof(double)), "hipMalloc(moments)");
         du = drho + n;
     }
-    hipError_t e = launch_moments(h->lattice, h->dtype, h->buf[h->cur], drho, du, h->d_chunks, h->nchunks, h->d_boxes,
+    const void* state = nullptr;
+    if (lbm_status st = natural_state(h, &state)) {
+        if (!on_device) (void)hipFree(drho);
+        return st;
+    }
+    hipError_t e = launch_moments(h->lattice, h->dtype, state, drho, du, h->d_chunks, h->nchunks, h->d_boxes,
                                   h->nsites, h->stream);
     if (e == hipSuccess && !on_device) {
         e = hipMemcpyAsync(rho, drho, n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
@@ -783,7 +865,9 @@ lbm_status lbm_totals(lbm_t h, double* out)
     if (!out) return fail(LBM_EINVAL, "out is NULL");
     if (!h->initialized) return fail(LBM_ESTATE, "lbm_totals before lbm_init");
     HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
-    hipError_t e = launch_totals(h->lattice, h->dtype, h->buf[h->cur], h->d_chunks, h->nchunks,
+    const void* state = nullptr;
+    if (lbm_status st = natural_state(h, &state)) return st;
+    hipError_t e = launch_totals(h->lattice, h->dtype, state, h->d_chunks, h->nchunks,
                                  h->d_box_chunk_begin, h->nbox, h->d_boxes, h->d_partial, h->d_out, h->stream);
     if (e != hipSuccess) return fail_hip(e, "totals kernels");
     HIP_TRY(hipMemcpyAsync(out, h->d_out, size_t(h->nbox) * 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream),
@@ -811,7 +895,13 @@ lbm_status lbm_residual(lbm_t h, const double* rho_ref, const double* u_ref, int
         if (t1) (void)hipFree(dr);
         return st;
     }
-    hipError_t e = launch_residual(h->lattice, h->dtype, h->buf[h->cur], dr, du, h->d_chunks, h->nchunks,
+    const void* state = nullptr;
+    if (lbm_status st = natural_state(h, &state)) {
+        if (t1) (void)hipFree(dr);
+        if (t2) (void)hipFree(du);
+        return st;
+    }
+    hipError_t e = launch_residual(h->lattice, h->dtype, state, dr, du, h->d_chunks, h->nchunks,
                                    h->d_boxes, h->nsites, h->d_partial, h->d_out, h->stream);
     double tmp[4] = {0, 0, 0, 0};
     if (e == hipSuccess) e = hipMemcpyAsync(tmp, h->d_out, 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream);
@@ -856,7 +946,9 @@ lbm_status lbm_get_state(lbm_t h, void* buf, size_t bytes)
     hd.payload_bytes = need - sizeof(CkptHeader);
     std::memcpy(buf, &hd, sizeof(hd));
     char* dst = static_cast<char*>(buf) + sizeof(hd);
-    HIP_TRY(hipMemcpyAsync(dst, h->buf[h->cur], size_t(h->lat.Q) * size_t(h->nsites) * h->elem, hipMemcpyDeviceToHost,
+    const void* state = nullptr;
+    if (lbm_status st = natural_state(h, &state)) return st;
+    HIP_TRY(hipMemcpyAsync(dst, state, size_t(h->lat.Q) * size_t(h->nsites) * h->elem, hipMemcpyDeviceToHost,
                            h->stream),
             "copy state to host");
     HIP_TRY(hipStreamSynchronize(h->stream), "get_state synchronize");

@@ -38,11 +38,17 @@ struct VecGeom {
 
 // A tile of the batched step: in box `box`, plane z, the x-rows y0 .. y0 +
 // rows - 1 (rows * nx <= threads per block), or, when nx exceeds the block,
-// the single row y0 from x0 on.
-struct TileDesc {
-    int box;
+// the single row y0 from x0 on.  The tile carries its box's geometry, first
+// site and relaxation factor, so a block starts after one 64-byte scalar load.
+struct alignas(64) TileDesc {
     int z, y0, rows, x0;
+    int nx, ny, nz;
+    float inv_nx;         // 1 / nx, for the lane -> (row, x) split of a tile
+    long long offset;     // the box's first global site
+    double omega;         // 1 - 1/tau of the box
+    int box;
 };
+static_assert(sizeof(TileDesc) == 64, "tile descriptor is one scalar load");
 
 struct BoxDesc {
     int nx, ny, nz;
@@ -67,13 +73,20 @@ hipError_t launch_init(int lat, int dtype, int K, const double* rho, const doubl
 // 2 filtered with the energy-flux term of weight theta).
 hipError_t launch_step(int lat, int dtype, int K, int kind, const void* src, void* dst, const StepGeom& geo,
                        double omega, double theta, int block, hipStream_t s);
+// The in-place step on one buffer: from the natural layout to the swapped one
+// (from_natural) or back (step.hpp, k_step_ip).
+hipError_t launch_step_ip(int lat, int dtype, int K, int kind, void* buf, bool from_natural, const StepGeom& geo,
+                          double omega, double theta, int block, hipStream_t s);
+// Swapped layout -> natural layout into another buffer (bit-exact permutation).
+hipError_t launch_unswap(int lat, int dtype, const void* src, void* dst, const StepGeom& geo, int block,
+                         hipStream_t s);
 // Sites per lane of the row-wave kernel for (lattice, dtype), 0 if that pair
 // has no row-wave form (a velocity component as large as V).
 int vec_sites_per_lane(int lat, int dtype);
 hipError_t launch_step_vec(int lat, int dtype, int K, int kind, const void* src, void* dst, const VecGeom& geo,
                            double omega, double theta, hipStream_t s);
 hipError_t launch_step_batch(int lat, int dtype, int K, int kind, const void* src, void* dst, const TileDesc* tiles,
-                             int ntiles, const BoxDesc* boxes, double theta, int block, int grid, hipStream_t s);
+                             int ntiles, double theta, int block, int grid, hipStream_t s);
 hipError_t launch_moments(int lat, int dtype, const void* src, double* rho, double* u, const ChunkDesc* chunks,
                           int nchunks, const BoxDesc* boxes, long long nsites, hipStream_t s);
 hipError_t launch_totals(int lat, int dtype, const void* src, const ChunkDesc* chunks, int nchunks,

@@ -295,6 +295,47 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s)
     return hipGetLastError();
 }
 
+// Swapped layout of the in-place step -> natural layout, into another buffer:
+// population j of site x is read from site x + c_j, tile row m(opp(j)).  A
+// pure permutation of stored values (bit-exact), single box.
+template <class L, class S>
+__global__ __launch_bounds__(256) void k_unswap(const S* __restrict__ src, S* __restrict__ dst, StepGeom geo)
+{
+    constexpr int RR = L::R;
+    const int y = blockIdx.y;
+    const int z = blockIdx.z;
+    const int x = int(blockIdx.x) * int(blockDim.x) + int(threadIdx.x);
+    if (x >= geo.nx) return;
+    const long long tile = (long long)L::Q * geo.nx;
+    int xw[2 * RR + 1], yw[2 * RR + 1], zw[2 * RR + 1];
+#pragma unroll
+    for (int k = 0; k <= 2 * RR; ++k) {
+        xw[k] = wrap_coord(x + k - RR, geo.nx);
+        yw[k] = wrap_coord(y + k - RR, geo.ny);
+        zw[k] = wrap_coord(z + k - RR, geo.nz);
+    }
+    S* q = dst + (long long)(z * geo.ny + y) * tile;
+    unroll<L::Q>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        constexpr int cx = L::c[j][0], cy = L::c[j][1], cz = L::c[j][2];
+        const int row = zw[RR + cz] * geo.ny + yw[RR + cy];
+        const S* p = src + row * tile + (long long)mem_row<L>(opp(j)) * geo.nx;
+        q[(long long)mem_row<L>(j) * geo.nx + x] = p[xw[RR + cx]];
+    });
+}
+
+hipError_t launch_unswap(int lat, int dtype, const void* src, void* dst, const StepGeom& geo, int block,
+                         hipStream_t s)
+{
+    return dispatch_ld(lat, dtype, [&](auto Lt, auto* Sp, auto) -> hipError_t {
+        using L = decltype(Lt);
+        using S = std::remove_pointer_t<decltype(Sp)>;
+        k_unswap<L, S><<<dim3(unsigned(geo.xblocks), unsigned(geo.ny), unsigned(geo.nz)), block, 0, s>>>(
+            static_cast<const S*>(src), static_cast<S*>(dst), geo);
+        return hipGetLastError();
+    });
+}
+
 // ---------------------------------------------------------------------------
 // Runtime-lattice entry points of the step kernels (instances compiled per
 // lattice in step_<lattice>.hip and batch_<lattice>.hip).
@@ -340,13 +381,23 @@ hipError_t launch_step_vec(int lat, int dtype, int K, int kind, const void* src,
     });
 }
 
-hipError_t launch_step_batch(int lat, int dtype, int K, int kind, const void* src, void* dst, const TileDesc* tiles,
-                             int ntiles, const BoxDesc* boxes, double theta, int block, int grid, hipStream_t s)
+hipError_t launch_step_ip(int lat, int dtype, int K, int kind, void* buf, bool from_natural, const StepGeom& geo,
+                          double omega, double theta, int block, hipStream_t s)
 {
     return by_pair(lat, dtype, [&](auto Lt, auto* Sp) {
         using L = decltype(Lt);
         using S = std::remove_pointer_t<decltype(Sp)>;
-        return launch_step_batch_l<L, S>(K, kind, src, dst, tiles, ntiles, boxes, theta, block, grid, s);
+        return launch_step_ip_l<L, S>(K, kind, buf, from_natural, geo, omega, theta, block, s);
+    });
+}
+
+hipError_t launch_step_batch(int lat, int dtype, int K, int kind, const void* src, void* dst, const TileDesc* tiles,
+                             int ntiles, double theta, int block, int grid, hipStream_t s)
+{
+    return by_pair(lat, dtype, [&](auto Lt, auto* Sp) {
+        using L = decltype(Lt);
+        using S = std::remove_pointer_t<decltype(Sp)>;
+        return launch_step_batch_l<L, S>(K, kind, src, dst, tiles, ntiles, theta, block, grid, s);
     });
 }
 

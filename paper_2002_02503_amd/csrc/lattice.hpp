@@ -171,6 +171,9 @@ static_assert(integer_weights_consistent<D3Q15>(), "D3Q15 weight quantum");
 static_assert(integer_weights_consistent<D3Q19>(), "D3Q19 weight quantum");
 static_assert(integer_weights_consistent<D3Q39>(), "D3Q39 weight quantum");
 
+// Index of the velocity opposite to c_i (rest first, then pairs (2k-1, 2k)).
+constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
 // Memory order of the populations inside a row tile: sorted by (c_z, c_y, c_x),
 // so the populations a step pulls from one neighbouring row tile are adjacent
 // rows of that tile.  mem_row(i) is the tile row of population i, mem_pop(m)

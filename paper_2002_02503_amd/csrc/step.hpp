@@ -59,6 +59,82 @@ __global__ __launch_bounds__(256) void k_step(const S* __restrict__ src, S* __re
     });
 }
 
+// ---------------------------------------------------------------------------
+// Fused step, single box, in place: one buffer, two alternating forms.
+// The state is in one of two layouts:
+//   natural: tile row m(i) of site x holds the post-collision population i of
+//            site x (the layout every other kernel reads and writes);
+//   swapped: the post-collision population i of site x sits at site x + c_i,
+//            in tile row m(opp(i)).
+// From natural, site x reads population i from site x - c_i, tile row m(i)
+// (the pull of k_step), collides, and writes its result for direction
+// opp(i) back to that same element, which leaves the state swapped.  From
+// swapped, site x finds population i in its own tile row m(opp(i)) and writes
+// population j to its own tile row m(j), which leaves it natural.  Each
+// element is read and then written by one thread only, so no second buffer is
+// needed and there is no race; two steps stream every population exactly as
+// two pull steps do, and the per-site arithmetic is that of k_step (the same
+// bits).  A row's reads and writes touch the same lines, which the memory
+// system serves faster than the two separate buffers of k_step.
+// ---------------------------------------------------------------------------
+
+template <class L, class S, int K, int KIND, bool FROM_NATURAL>
+__global__ __launch_bounds__(256) void k_step_ip(S* __restrict__ buf, StepGeom geo, typename Store<S>::R omega,
+                                                 typename Store<S>::R theta)
+{
+    using ST = Store<S>;
+    using R = typename ST::R;
+    constexpr bool PROJ = !std::is_same<R, double>::value;
+    constexpr int RR = L::R;
+
+    const int y = blockIdx.y;
+    const int z = blockIdx.z;
+    const int x = int(blockIdx.x) * int(blockDim.x) + int(threadIdx.x);
+    if (x >= geo.nx) return;
+    const long long tile = (long long)L::Q * geo.nx;
+
+    R g[L::Q];
+    if constexpr (FROM_NATURAL) {
+        int xw[2 * RR + 1], yw[2 * RR + 1], zw[2 * RR + 1];
+#pragma unroll
+        for (int k = 0; k <= 2 * RR; ++k) {
+            xw[k] = wrap_coord(x + k - RR, geo.nx);
+            yw[k] = wrap_coord(y + k - RR, geo.ny);
+            zw[k] = wrap_coord(z + k - RR, geo.nz);
+        }
+        // element of population i at site x - c_i: uniform row pointer, lane offset
+        auto elem = [&](auto M) -> S* {
+            constexpr int m = decltype(M)::value;
+            constexpr int i = mem_pop<L>(m);
+            constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
+            const int row = zw[RR - cz] * geo.ny + yw[RR - cy];
+            return at32(buf + row * tile + (long long)m * geo.nx, unsigned(xw[RR - cx]));
+        };
+        unroll<L::Q>([&](auto M) {  // in tile-row order
+            constexpr int i = mem_pop<L>(decltype(M)::value);
+            g[i] = load_population<ST, L::c[i][0]>(elem(M));
+        });
+        collide_site<L, K, KIND, PROJ, R>(g, omega, theta);
+        unroll<L::Q>([&](auto M) {
+            constexpr int i = mem_pop<L>(decltype(M)::value);
+            const R v = g[opp(i)];
+            if constexpr (L::c[i][0] == 0) ST::put_nt(elem(M), v);
+            else ST::put(elem(M), v);
+        });
+    } else {
+        S* q = buf + (long long)(z * geo.ny + y) * tile;
+        unroll<L::Q>([&](auto M) {
+            constexpr int m = decltype(M)::value;
+            g[opp(mem_pop<L>(m))] = ST::get_nt(at32(q + (long long)m * geo.nx, unsigned(x)));
+        });
+        collide_site<L, K, KIND, PROJ, R>(g, omega, theta);
+        unroll<L::Q>([&](auto M) {
+            constexpr int m = decltype(M)::value;
+            ST::put_nt(at32(q + (long long)m * geo.nx, unsigned(x)), g[mem_pop<L>(m)]);
+        });
+    }
+}
+
 template <class L, class S, int K, int KIND>
 __global__ __launch_bounds__(256) void k_step_vec(const S* __restrict__ src, S* __restrict__ dst, VecGeom geo,
                                                   typename Store<S>::R omega, typename Store<S>::R theta)
@@ -145,6 +221,23 @@ hipError_t launch_step_l(int K, int kind, const void* src, void* dst, const Step
         constexpr int KD = decltype(Kind)::value;
         k_step<L, S, KK, KD><<<dim3(unsigned(geo.xblocks), unsigned(geo.ny), unsigned(geo.nz)), block, 0, s>>>(
             static_cast<const S*>(src), static_cast<S*>(dst), geo, R(omega), R(theta));
+        return hipGetLastError();
+    });
+}
+
+template <class L, class S>
+hipError_t launch_step_ip_l(int K, int kind, void* buf, bool from_natural, const StepGeom& geo, double omega,
+                            double theta, int block, hipStream_t s)
+{
+    return dispatch_pair<L, S>(K, kind, [&](auto, auto*, auto Kc, auto Kind) -> hipError_t {
+        using R = typename Store<S>::R;
+        constexpr int KK = decltype(Kc)::value;
+        constexpr int KD = decltype(Kind)::value;
+        const dim3 grid(unsigned(geo.xblocks), unsigned(geo.ny), unsigned(geo.nz));
+        if (from_natural)
+            k_step_ip<L, S, KK, KD, true><<<grid, block, 0, s>>>(static_cast<S*>(buf), geo, R(omega), R(theta));
+        else
+            k_step_ip<L, S, KK, KD, false><<<grid, block, 0, s>>>(static_cast<S*>(buf), geo, R(omega), R(theta));
         return hipGetLastError();
     });
 }

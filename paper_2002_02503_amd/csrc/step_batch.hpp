@@ -20,7 +20,7 @@ namespace lbm {
 template <class L, class S, int K, int KIND>
 __global__ __launch_bounds__(256) void k_step_batch(const S* __restrict__ src, S* __restrict__ dst,
                                                     const TileDesc* __restrict__ tiles, int ntiles,
-                                                    const BoxDesc* __restrict__ boxes, typename Store<S>::R theta)
+                                                    typename Store<S>::R theta)
 {
     using ST = Store<S>;
     using R = typename ST::R;
@@ -28,8 +28,7 @@ __global__ __launch_bounds__(256) void k_step_batch(const S* __restrict__ src, S
     constexpr int RR = L::R;
 
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const TileDesc td = tiles[t];
-        const BoxDesc b = boxes[td.box];
+        const TileDesc b = tiles[t];
         const int tid = int(threadIdx.x);
         int r, x;
         if (b.nx <= int(blockDim.x)) {
@@ -39,11 +38,11 @@ __global__ __launch_bounds__(256) void k_step_batch(const S* __restrict__ src, S
             x = tid - r * b.nx;
         } else {
             r = 0;
-            x = td.x0 + tid;
+            x = b.x0 + tid;
         }
-        if (r >= td.rows || x >= b.nx) continue;
-        const int y = td.y0 + r;
-        const int z = td.z;
+        if (r >= b.rows || x >= b.nx) continue;
+        const int y = b.y0 + r;
+        const int z = b.z;
         const S* sb = src + (long long)L::Q * b.offset;
         S* db = dst + (long long)L::Q * b.offset;
 
@@ -83,7 +82,7 @@ __global__ __launch_bounds__(256) void k_step_batch(const S* __restrict__ src, S
 
 template <class L, class S>
 hipError_t launch_step_batch_l(int K, int kind, const void* src, void* dst, const TileDesc* tiles, int ntiles,
-                               const BoxDesc* boxes, double theta, int block, int grid, hipStream_t s)
+                               double theta, int block, int grid, hipStream_t s)
 {
     return dispatch_pair<L, S>(K, kind, [&](auto, auto*, auto Kc, auto Kind) -> hipError_t {
         using R = typename Store<S>::R;
@@ -91,7 +90,7 @@ hipError_t launch_step_batch_l(int K, int kind, const void* src, void* dst, cons
         constexpr int KD = decltype(Kind)::value;
         const int g = (grid > 0 && grid < ntiles) ? grid : ntiles;
         k_step_batch<L, S, KK, KD><<<g, block, 0, s>>>(static_cast<const S*>(src), static_cast<S*>(dst), tiles,
-                                                       ntiles, boxes, R(theta));
+                                                       ntiles, R(theta));
         return hipGetLastError();
     });
 }

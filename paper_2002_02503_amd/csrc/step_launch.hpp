@@ -17,6 +17,12 @@ template <class L, class S>
 hipError_t launch_step_l(int K, int kind, const void* src, void* dst, const StepGeom& geo, double omega,
                          double theta, int block, hipStream_t s);
 
+// Single box, in place: from the natural layout to the swapped one
+// (from_natural) or back (see k_step_ip).
+template <class L, class S>
+hipError_t launch_step_ip_l(int K, int kind, void* buf, bool from_natural, const StepGeom& geo, double omega,
+                            double theta, int block, hipStream_t s);
+
 // Sites per lane of the row-wave form (0: none for this pair).
 template <class L, class S>
 int vec_sites_l();
@@ -29,18 +35,20 @@ hipError_t launch_step_vec_l(int K, int kind, const void* src, void* dst, const 
 // Batch of boxes: a fixed grid walks the tile table.
 template <class L, class S>
 hipError_t launch_step_batch_l(int K, int kind, const void* src, void* dst, const TileDesc* tiles, int ntiles,
-                               const BoxDesc* boxes, double theta, int block, int grid, hipStream_t s);
+                               double theta, int block, int grid, hipStream_t s);
 
 #define LBM_DECLARE_STEP_INSTANCES(EXT, L, S)                                                                    \
     EXT template hipError_t launch_step_l<L, S>(int, int, const void*, void*, const StepGeom&, double, double,  \
                                                 int, hipStream_t);                                             \
+    EXT template hipError_t launch_step_ip_l<L, S>(int, int, void*, bool, const StepGeom&, double, double, int, \
+                                                   hipStream_t);                                               \
     EXT template int vec_sites_l<L, S>();                                                                      \
     EXT template hipError_t launch_step_vec_l<L, S>(int, int, const void*, void*, const VecGeom&, double,      \
                                                     double, hipStream_t);
 
 #define LBM_DECLARE_BATCH_INSTANCES(EXT, L, S)                                                                 \
     EXT template hipError_t launch_step_batch_l<L, S>(int, int, const void*, void*, const TileDesc*, int,    \
-                                                      const BoxDesc*, double, int, int, hipStream_t);
+                                                      double, int, int, hipStream_t);
 
 #define LBM_EXTERN_PAIR(L, S)                  \
     LBM_DECLARE_STEP_INSTANCES(extern, L, S)   \

@@ -1,0 +1,134 @@
+"""The in-place step (one buffer, two alternating layouts of the state) against
+the two-buffer step: the same bits after any number of steps, whatever the
+graph chunking; readers (moments, totals, residual, checkpoints) see the
+natural layout at odd and even times; and parity with the oracle."""
+import numpy as np
+import pytest
+
+from gpu_common import BOUND, rel_rho, rel_u, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _fields(D, dims, seed, amp=0.05):
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = dims
+    shape = (nz, ny, nx)
+    return 1.0 + rng.uniform(-0.01, 0.01, size=shape), rng.uniform(-amp, amp, size=(D,) + shape)
+
+
+CASES = [
+    ("D3Q19", (256, 5, 4), "fp32", {}),
+    ("D3Q19", (70, 9, 6), "fp16", {}),
+    ("D3Q19", (37, 6, 5), "bf16", {"collision": "bgk"}),
+    ("D3Q19", (64, 7, 3), "fp64", {"theta": 0.5}),
+    ("D3Q15", (300, 4, 3), "fp32", {}),
+    ("D2Q9", (300, 7, 1), "fp32", {}),
+    ("D3Q39", (260, 5, 4), "fp32", {}),
+    ("D3Q39", (40, 6, 7), "fp16", {"K": 5}),
+]
+
+
+@pytest.mark.parametrize("lattice,dims,dtype,kw", CASES)
+@pytest.mark.parametrize("steps", [1, 2, 7, 40])
+def test_in_place_equals_two_buffer_step(lattice, dims, dtype, kw, steps):
+    D = 2 if lattice == "D2Q9" else 3
+    rho, u = _fields(D, dims, seed=steps + sum(dims))
+    a = run_gpu(lattice, dims, 0.6, dtype, rho, u, steps, kernel="in_place", **kw)
+    b = run_gpu(lattice, dims, 0.6, dtype, rho, u, steps, kernel="scalar", **kw)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("chunk", [1, 3, 32])
+def test_in_place_graph_chunks(chunk):
+    """Odd and even graph chunks alternate the layout inside a captured graph."""
+    dims = (96, 5, 6)
+    rho, u = _fields(3, dims, seed=chunk)
+    a = run_gpu("D3Q19", dims, 0.57, "fp32", rho, u, 77, kernel="in_place", graph_chunk=chunk)
+    b = run_gpu("D3Q19", dims, 0.57, "fp32", rho, u, 77, kernel="scalar")
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("lattice,dims", [("D3Q19", (1, 2, 3)), ("D3Q19", (2, 2, 2)), ("D3Q39", (1, 1, 1)),
+                                          ("D3Q39", (2, 1, 5)), ("D3Q39", (5, 3, 2)), ("D2Q9", (2, 3, 1))])
+def test_in_place_degenerate_boxes(lattice, dims):
+    """Boxes shorter than the velocities: every element is still read and
+    written by exactly one thread."""
+    D = 2 if lattice == "D2Q9" else 3
+    rho, u = _fields(D, dims, seed=3)
+    r_ref, u_ref = run_oracle(lattice, dims, 0.7, rho, u, 25)
+    for dtype in ["fp64", "fp32"]:
+        r, uu = run_gpu(lattice, dims, 0.7, dtype, rho, u, 25, kernel="in_place")
+        assert rel_u(uu, u_ref) < BOUND[dtype] and rel_rho(r, r_ref) < BOUND[dtype]
+        r2, u2 = run_gpu(lattice, dims, 0.7, dtype, rho, u, 25, kernel="scalar")
+        assert np.array_equal(r, r2) and np.array_equal(uu, u2)
+
+
+def test_in_place_matches_oracle():
+    dims = (200, 6, 5)
+    rho, u = _fields(3, dims, seed=11)
+    r_ref, u_ref = run_oracle("D3Q19", dims, 0.55, rho, u, 31, mode="closed")
+    for dtype in ["fp64", "fp32", "fp16", "bf16"]:
+        r, uu = run_gpu("D3Q19", dims, 0.55, dtype, rho, u, 31, kernel="in_place")
+        assert rel_u(uu, u_ref) < BOUND[dtype] and rel_rho(r, r_ref) < BOUND[dtype]
+
+
+def test_readers_at_odd_and_even_times():
+    """Moments, totals, residual and checkpoints after odd and even step
+    counts equal those of the two-buffer step, and a checkpoint taken at an odd
+    time resumes bit for bit in either kernel."""
+    from paper_2002_02503_amd import lbm
+
+    dims = (64, 9, 7)
+    rho, u = _fields(3, dims, seed=5)
+    with lbm.Simulation("D3Q19", dims, 0.6, dtype="fp32", kernel="in_place") as ip, \
+            lbm.Simulation("D3Q19", dims, 0.6, dtype="fp32", kernel="scalar") as sc:
+        ip.init(rho, u)
+        sc.init(rho, u)
+        for n in [1, 1, 3, 2]:
+            ip.step(n)
+            sc.step(n)
+            r1, u1 = ip.moments()
+            r2, u2 = sc.moments()
+            assert np.array_equal(r1, r2) and np.array_equal(u1, u2)
+            assert np.array_equal(ip.totals(), sc.totals())
+            assert ip.residual(r2, u2) == sc.residual(r2, u2)
+            assert np.array_equal(ip.get_state(), sc.get_state())
+            # reading does not disturb the state: stepping on gives the same bits
+        assert ip.t == 7
+        ck = ip.get_state()
+        ip.step(5)
+        sc.step(5)
+        ref = sc.moments()
+        for kernel in ["in_place", "scalar"]:
+            with lbm.Simulation("D3Q19", dims, 0.6, dtype="fp32", kernel=kernel) as other:
+                other.set_state(ck)
+                assert other.t == 7
+                other.step(5)
+                r, uu = other.moments()
+                assert np.array_equal(r, ref[0]) and np.array_equal(uu, ref[1])
+
+
+def test_in_place_is_rejected_for_batches():
+    from paper_2002_02503_amd import lbm
+
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.Simulation("D3Q19", [(8, 8, 8), (9, 9, 9)], [0.6, 0.7], kernel="in_place")
+    assert e.value.name == "LBM_EINVAL"
+
+
+def test_tuning_across_layouts_keeps_the_state():
+    """The tuner switches between the in-place and two-buffer kernels with the
+    state at an odd time; afterwards the run continues bit for bit."""
+    from paper_2002_02503_amd import lbm
+
+    dims = (128, 6, 5)
+    rho, u = _fields(3, dims, seed=8)
+    ref = run_gpu("D3Q19", dims, 0.6, "fp32", rho, u, 13, kernel="scalar")
+    with lbm.Simulation("D3Q19", dims, 0.6, dtype="fp32", kernel="in_place") as sim:
+        sim.init(rho, u).step(3)
+        sim.tune(steps=4)
+        assert sim.t == 3
+        sim.step(10)
+        r, uu = sim.moments()
+    assert np.array_equal(r, ref[0]) and np.array_equal(uu, ref[1])
