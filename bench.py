@@ -26,7 +26,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS & % HBM roofline, D3Q19 256³ FP32 vs FP16-storage at stated error"
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E peak
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_d3q19_256_fp32.json")
+def traffic_file(kernel: str) -> str:
+    """Committed counter summary of the headline step for one kernel variant."""
+    return os.path.join(ROOT, "profiles", f"traffic_d3q19_256_fp32_{kernel}.json")
 # what decides the step kernel's machine code: its sources and the compiler flags
 def _kernel_sources() -> list:
     """Every source that goes into the device code (all of csrc/ except the
@@ -92,13 +94,16 @@ def measure_box(lattice, dims, tau, dtype, rho, u, steps, warmup, tune=True, **k
             "block": info["block"], "grid": info["grid"]}
 
 
-def traffic_per_launch():
-    """HBM bytes per launch of the FP32 256^3 step from the committed rocprofv3
-    counter summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel
-    calibration), or None when absent or taken on other kernel sources."""
-    if not os.path.exists(TRAFFIC_FILE):
+def traffic_per_launch(kernel: str):
+    """HBM bytes per launch of the FP32 256^3 step of a kernel variant from the
+    committed rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, scaled by the
+    copy-kernel calibration), or None when absent or taken on other kernel
+    sources.  For the in-place variant a launch is one of its two alternating
+    forms, averaged over both."""
+    path = traffic_file(kernel)
+    if not os.path.exists(path):
         return None, "no counter summary"
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         t = json.load(f)
     if t.get("source_hash") != source_hash():
         return None, "kernel changed since the counters were taken"
@@ -199,7 +204,7 @@ def main():
         head = measure_box("D3Q19", (256, 256, 256), tau, "fp32", rho, u, args.steps, args.warmup, tune=False, **pin)
     log(f"headline: {head['value']:.0f} MLUPS with the {head['kernel']} step, block {head['block']}")
     nsites = head["nsites"]
-    traffic, traffic_src = traffic_per_launch()
+    traffic, traffic_src = traffic_per_launch(head["kernel"])
     roofline = {"bound": "hbm", "achieved": head["achieved_GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": head["achieved_GBs"] / PEAK_HBM_GBS, "traffic": traffic,
                 "algorithmic_bytes_per_launch": head["bytes_per_site_update"] * nsites,

@@ -74,7 +74,7 @@ typedef enum {
     LBM_KERNEL_ROW_WAVE = 2,  /* V sites per lane, 8/16-byte accesses, x-neighbours by lane shuffle */
     LBM_KERNEL_IN_PLACE = 3   /* one site per thread on one buffer: each step reads and writes the same
                                  elements, alternating between two layouts of the state (bit-identical
-                                 results; readers see the natural layout) */
+                                 results, half the memory) */
 } lbm_kernel;
 
 typedef struct {
@@ -175,11 +175,14 @@ lbm_status lbm_set_launch(lbm_t h, int32_t block, int32_t grid);
  * LBM_KERNEL_ROW_WAVE needs nx to be a multiple of the sites per lane V (4 for
  * FP32/FP16/BF16, 2 for FP64) with nx / V <= 64, and V above the largest
  * velocity component (so FP64 D3Q39 has none); else LBM_EINVAL.
- * LBM_KERNEL_IN_PLACE steps the state inside one of the two buffers; on odd
- * step counts the state is kept in a swapped layout, and every call that reads
- * it (moments, totals, residual, checkpoint) first rewrites it into the
- * natural layout in the other buffer.  Batches always use the tiled batched
- * kernel.  Only before lbm_init. */
+ * LBM_KERNEL_IN_PLACE steps the state inside one buffer: with library-owned
+ * memory only one population buffer is allocated, so a box of twice the size
+ * fits.  After an odd number of its steps the state is kept in a swapped
+ * layout (population i of site x at site x + c_i, tile row m(opp(i))); the
+ * moments, totals and residual read it as it is, and lbm_get_state returns the
+ * natural layout (rearranged on the host).  Switching kernels later (lbm_tune)
+ * allocates the second buffer.  Batches always use the tiled batched kernel.
+ * Only before lbm_init. */
 lbm_status lbm_set_kernel(lbm_t h, int32_t kernel);
 
 /* Autotune the step's launch: time every candidate (single box: the scalar

@@ -12,7 +12,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <new>
 #include <sstream>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -367,22 +369,32 @@ lbm_status create_common(lbm_t* out, int32_t lattice, int32_t nbox, const int64_
     return LBM_OK;
 }
 
-lbm_status ensure_buffers(lbm_ctx* h)
+lbm_status alloc_buffer(lbm_ctx* h, int k)
 {
-    if (h->buf[0] && h->buf[1]) return LBM_OK;
-    void* a = nullptr;
-    void* b = nullptr;
-    hipError_t e = hipMalloc(&a, h->state_bytes);
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, h->state_bytes);
     if (e != hipSuccess) return fail_hip(e, "hipMalloc(population buffer)");
-    e = hipMalloc(&b, h->state_bytes);
-    if (e != hipSuccess) {
-        (void)hipFree(a);
-        return fail_hip(e, "hipMalloc(population buffer)");
-    }
-    h->buf[0] = a;
-    h->buf[1] = b;
+    h->buf[k] = p;
     h->owns_buf = true;
     return LBM_OK;
+}
+
+// The population buffers, unless the caller bound its own.  The in-place step
+// needs only buf[0]; buf[1] then comes later, if ever (ensure_second).
+lbm_status ensure_buffers(lbm_ctx* h)
+{
+    if (!h->buf[0])
+        if (lbm_status st = alloc_buffer(h, 0)) return st;
+    const bool one = is_single(h) && h->kernel == LBM_KERNEL_IN_PLACE;
+    if (!h->buf[1] && !one)
+        if (lbm_status st = alloc_buffer(h, 1)) return st;
+    return LBM_OK;
+}
+
+lbm_status ensure_second(lbm_ctx* h)
+{
+    if (h->buf[1]) return LBM_OK;
+    return alloc_buffer(h, 1);
 }
 
 bool in_place(const lbm_ctx* h) { return is_single(h) && effective_kernel(h) == LBM_KERNEL_IN_PLACE; }
@@ -428,40 +440,58 @@ hipError_t launch_one(lbm_ctx* h, int parity, hipStream_t s)
                              block, h->grid, s);
 }
 
-// The current state in the natural layout, for the calls that read it: the
-// buffer that holds it, or, when the in-place step left it swapped, the other
-// buffer after the swap is undone into it (the state itself stays put).
-lbm_status natural_state(lbm_ctx* h, const void** out)
+// Where the current state is, and whether the in-place step left it in the
+// swapped layout (after an odd number of its steps).
+void state_view(const lbm_ctx* h, const void** state, bool* swapped)
 {
-    if (!in_place(h)) {
-        *out = h->buf[h->cur];
-        return LBM_OK;
+    if (in_place(h)) {
+        *state = h->buf[0];
+        *swapped = (h->cur == 1);
+    } else {
+        *state = h->buf[h->cur];
+        *swapped = false;
     }
-    if (h->cur == 0) {
-        *out = h->buf[0];
-        return LBM_OK;
-    }
-    const int block = effective_block(h);
-    hipError_t e = launch_unswap(h->lattice, h->dtype, h->buf[0], h->buf[1], single_geom(h, block), block, h->stream);
-    if (e != hipSuccess) return fail_hip(e, "unswap kernel");
-    *out = h->buf[1];
-    return LBM_OK;
 }
 
 // Bring the state into buf[0] in the natural layout (cur = 0), valid for
 // every step kernel, before the kernel choice changes on an initialised
-// handle.  Swaps the two buffer pointers where that suffices.
+// handle: undo the swap of the in-place step into the other buffer, then swap
+// the two buffer pointers.
 lbm_status canonicalize(lbm_ctx* h)
 {
     if (!h->initialized || h->cur == 0) return LBM_OK;
     if (in_place(h)) {
-        const void* nat = nullptr;
-        if (lbm_status st = natural_state(h, &nat)) return st;
+        if (lbm_status st = ensure_second(h)) return st;
+        const int block = effective_block(h);
+        hipError_t e =
+            launch_unswap(h->lattice, h->dtype, h->buf[0], h->buf[1], single_geom(h, block), block, h->stream);
+        if (e != hipSuccess) return fail_hip(e, "unswap kernel");
     }
     std::swap(h->buf[0], h->buf[1]);
     h->cur = 0;
     drop_graphs(h);
     return LBM_OK;
+}
+
+// Host copy of the swapped layout -> natural layout (single box): population
+// j of site x comes from site x + c_j, tile row m(opp(j)).
+void unswap_host(const lbm_ctx* h, const char* src, char* dst)
+{
+    const LatticeInfo& L = h->lat;
+    const int64_t nx = h->dims[0], ny = h->dims[1], nz = h->dims[2];
+    const size_t e = h->elem;
+    const int64_t tile = int64_t(L.Q) * nx;
+    auto wrap = [](int64_t v, int64_t n) { return ((v % n) + n) % n; };
+    for (int64_t z = 0; z < nz; ++z)
+        for (int64_t y = 0; y < ny; ++y)
+            for (int j = 0; j < L.Q; ++j) {
+                const int jo = (j == 0) ? 0 : ((j & 1) ? j + 1 : j - 1);
+                const int64_t zs = wrap(z + L.c[j * 3 + 2], nz), ys = wrap(y + L.c[j * 3 + 1], ny);
+                const char* s_row = src + ((zs * ny + ys) * tile + int64_t(L.mrow[jo]) * nx) * e;
+                char* d_row = dst + ((z * ny + y) * tile + int64_t(L.mrow[j]) * nx) * e;
+                for (int64_t x = 0; x < nx; ++x)
+                    std::memcpy(d_row + x * e, s_row + wrap(x + L.c[j * 3], nx) * e, e);
+            }
 }
 
 lbm_status build_graph(lbm_ctx* h, int parity)
@@ -657,6 +687,8 @@ lbm_status lbm_prepare(lbm_t h)
     if (lbm_status st = check_handle(h)) return st;
     if (!h->initialized) return fail(LBM_ESTATE, "lbm_prepare before lbm_init");
     HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+    if (!in_place(h))
+        if (lbm_status st = ensure_second(h)) return st;
     for (int p = 0; p < 2; ++p)
         if (lbm_status st = build_graph(h, p)) return st;
     return LBM_OK;
@@ -669,6 +701,8 @@ lbm_status lbm_step(lbm_t h, int64_t n)
     if (!h->initialized) return fail(LBM_ESTATE, "lbm_step before lbm_init");
     if (n == 0) return LBM_OK;
     HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+    if (!in_place(h))
+        if (lbm_status st = ensure_second(h)) return st;
     if (lbm_status st = build_tiles(h, effective_block(h))) return st;
     const int G = h->graph_chunk;
     int64_t left = n;
@@ -842,12 +876,10 @@ lbm_status lbm_moments(lbm_t h, double* rho, double* u, int32_t on_device)
         du = drho + n;
     }
     const void* state = nullptr;
-    if (lbm_status st = natural_state(h, &state)) {
-        if (!on_device) (void)hipFree(drho);
-        return st;
-    }
-    hipError_t e = launch_moments(h->lattice, h->dtype, state, drho, du, h->d_chunks, h->nchunks, h->d_boxes,
-                                  h->nsites, h->stream);
+    bool swapped = false;
+    state_view(h, &state, &swapped);
+    hipError_t e = launch_moments(h->lattice, h->dtype, state, swapped, drho, du, h->d_chunks, h->nchunks,
+                                  h->d_boxes, h->nsites, h->stream);
     if (e == hipSuccess && !on_device) {
         e = hipMemcpyAsync(rho, drho, n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
         if (e == hipSuccess) e = hipMemcpyAsync(u, du, n * D * sizeof(double), hipMemcpyDeviceToHost, h->stream);
@@ -866,8 +898,9 @@ lbm_status lbm_totals(lbm_t h, double* out)
     if (!h->initialized) return fail(LBM_ESTATE, "lbm_totals before lbm_init");
     HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
     const void* state = nullptr;
-    if (lbm_status st = natural_state(h, &state)) return st;
-    hipError_t e = launch_totals(h->lattice, h->dtype, state, h->d_chunks, h->nchunks,
+    bool swapped = false;
+    state_view(h, &state, &swapped);
+    hipError_t e = launch_totals(h->lattice, h->dtype, state, swapped, h->d_chunks, h->nchunks,
                                  h->d_box_chunk_begin, h->nbox, h->d_boxes, h->d_partial, h->d_out, h->stream);
     if (e != hipSuccess) return fail_hip(e, "totals kernels");
     HIP_TRY(hipMemcpyAsync(out, h->d_out, size_t(h->nbox) * 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream),
@@ -896,12 +929,9 @@ lbm_status lbm_residual(lbm_t h, const double* rho_ref, const double* u_ref, int
         return st;
     }
     const void* state = nullptr;
-    if (lbm_status st = natural_state(h, &state)) {
-        if (t1) (void)hipFree(dr);
-        if (t2) (void)hipFree(du);
-        return st;
-    }
-    hipError_t e = launch_residual(h->lattice, h->dtype, state, dr, du, h->d_chunks, h->nchunks,
+    bool swapped = false;
+    state_view(h, &state, &swapped);
+    hipError_t e = launch_residual(h->lattice, h->dtype, state, swapped, dr, du, h->d_chunks, h->nchunks,
                                    h->d_boxes, h->nsites, h->d_partial, h->d_out, h->stream);
     double tmp[4] = {0, 0, 0, 0};
     if (e == hipSuccess) e = hipMemcpyAsync(tmp, h->d_out, 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream);
@@ -947,11 +977,25 @@ lbm_status lbm_get_state(lbm_t h, void* buf, size_t bytes)
     std::memcpy(buf, &hd, sizeof(hd));
     char* dst = static_cast<char*>(buf) + sizeof(hd);
     const void* state = nullptr;
-    if (lbm_status st = natural_state(h, &state)) return st;
-    HIP_TRY(hipMemcpyAsync(dst, state, size_t(h->lat.Q) * size_t(h->nsites) * h->elem, hipMemcpyDeviceToHost,
-                           h->stream),
-            "copy state to host");
-    HIP_TRY(hipStreamSynchronize(h->stream), "get_state synchronize");
+    bool swapped = false;
+    state_view(h, &state, &swapped);
+    const size_t payload = size_t(h->lat.Q) * size_t(h->nsites) * h->elem;
+    if (!swapped) {
+        HIP_TRY(hipMemcpyAsync(dst, state, payload, hipMemcpyDeviceToHost, h->stream), "copy state to host");
+        HIP_TRY(hipStreamSynchronize(h->stream), "get_state synchronize");
+    } else {
+        // the in-place step left the state swapped: copy it out as it is and
+        // put it into the natural layout on the host (no second device buffer)
+        std::vector<char> tmp;
+        try {
+            tmp.resize(payload);
+        } catch (const std::bad_alloc&) {
+            return fail(LBM_ENOMEM, "host staging for the checkpoint");
+        }
+        HIP_TRY(hipMemcpyAsync(tmp.data(), state, payload, hipMemcpyDeviceToHost, h->stream), "copy state to host");
+        HIP_TRY(hipStreamSynchronize(h->stream), "get_state synchronize");
+        unswap_host(h, tmp.data(), dst);
+    }
     return LBM_OK;
 }
 

@@ -87,14 +87,16 @@ hipError_t launch_step_vec(int lat, int dtype, int K, int kind, const void* src,
                            double omega, double theta, hipStream_t s);
 hipError_t launch_step_batch(int lat, int dtype, int K, int kind, const void* src, void* dst, const TileDesc* tiles,
                              int ntiles, double theta, int block, int grid, hipStream_t s);
-hipError_t launch_moments(int lat, int dtype, const void* src, double* rho, double* u, const ChunkDesc* chunks,
-                          int nchunks, const BoxDesc* boxes, long long nsites, hipStream_t s);
-hipError_t launch_totals(int lat, int dtype, const void* src, const ChunkDesc* chunks, int nchunks,
+// Readers of the stored state.  swapped: the state is in the swapped layout
+// the in-place step leaves after an odd number of steps (single box).
+hipError_t launch_moments(int lat, int dtype, const void* src, bool swapped, double* rho, double* u,
+                          const ChunkDesc* chunks, int nchunks, const BoxDesc* boxes, long long nsites, hipStream_t s);
+hipError_t launch_totals(int lat, int dtype, const void* src, bool swapped, const ChunkDesc* chunks, int nchunks,
                          const int* box_chunk_begin, int nbox, const BoxDesc* boxes, double* partial, double* out,
                          hipStream_t s);
-hipError_t launch_residual(int lat, int dtype, const void* src, const double* rho_ref, const double* u_ref,
-                           const ChunkDesc* chunks, int nchunks, const BoxDesc* boxes, long long nsites,
-                           double* partial, double* out, hipStream_t s);
+hipError_t launch_residual(int lat, int dtype, const void* src, bool swapped, const double* rho_ref,
+                           const double* u_ref, const ChunkDesc* chunks, int nchunks, const BoxDesc* boxes,
+                           long long nsites, double* partial, double* out, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 
 // Host copy of a lattice's tables (from the compile-time descriptors).
@@ -103,6 +105,7 @@ struct LatticeInfo {
     double T0;
     std::vector<int> c;     // Q * 3
     std::vector<double> w;  // Q
+    std::vector<int> mrow;  // Q: tile row m(i) of population i
 };
 bool lattice_info(int lat, LatticeInfo* out);
 

@@ -51,7 +51,8 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ rho, co
         equilibrium_scaled<L, K, double>(rho[s] - 1.0, ux, uy, uz, g);
         unroll<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            ST::put_d(base + e + (long long)mem_row<L>(i) * b.nx, g[i]);
+            constexpr int m = mem_row<L>(i);
+            ST::put_d(base + e + (long long)m * b.nx, g[i]);
         });
     }
 }
@@ -67,7 +68,8 @@ __device__ __forceinline__ void site_moments(const S* __restrict__ p, int nx, do
     unroll<L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
-        const double gi = double(ST::get(p + (long long)mem_row<L>(i) * nx));
+        constexpr int m = mem_row<L>(i);
+        const double gi = double(ST::get(p + (long long)m * nx));
         dsum += gi;
         if constexpr (cx != 0) j[0] += double(cx) * gi;
         if constexpr (cy != 0) j[1] += double(cy) * gi;
@@ -80,7 +82,47 @@ __device__ __forceinline__ void site_moments(const S* __restrict__ p, int nx, do
     j[2] /= double(L::S);
 }
 
+// The same for a box whose state the in-place step left in the swapped layout:
+// population i of site (x, y, z) sits at site (x, y, z) + c_i, tile row
+// m(opp(i)).  `local` is the site's index inside its box.
 template <class L, class S>
+__device__ __forceinline__ void swapped_site_moments(const S* __restrict__ base, long long local, const BoxDesc& b,
+                                                     double& dsum, double (&j)[3])
+{
+    using ST = Store<S>;
+    const long long r = local / b.nx;
+    const int x = int(local - r * b.nx);
+    const int y = int(r % b.ny);
+    const int z = int(r / b.ny);
+    const long long tile = (long long)L::Q * b.nx;
+    dsum = 0.0;
+    j[0] = j[1] = j[2] = 0.0;
+    unroll<L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
+        constexpr int m = mem_row<L>(opp(i));
+        const int xs = wrap_coord(x + cx, b.nx), ys = wrap_coord(y + cy, b.ny), zs = wrap_coord(z + cz, b.nz);
+        const double gi = double(ST::get(base + ((long long)zs * b.ny + ys) * tile + (long long)m * b.nx + xs));
+        dsum += gi;
+        if constexpr (cx != 0) j[0] += double(cx) * gi;
+        if constexpr (cy != 0) j[1] += double(cy) * gi;
+        if constexpr (cz != 0) j[2] += double(cz) * gi;
+    });
+    dsum /= double(L::S);
+    j[0] /= double(L::S);
+    j[1] /= double(L::S);
+    j[2] /= double(L::S);
+}
+
+template <class L, class S, bool SWAPPED>
+__device__ __forceinline__ void stored_site_moments(const S* __restrict__ base, long long local, const BoxDesc& b,
+                                                    double& dsum, double (&j)[3])
+{
+    if constexpr (SWAPPED) swapped_site_moments<L, S>(base, local, b, dsum, j);
+    else site_moments<L, S>(base + site_elem(local, b.nx, L::Q), b.nx, dsum, j);
+}
+
+template <class L, class S, bool SWAPPED>
 __global__ __launch_bounds__(256) void k_moments(const S* __restrict__ src, double* __restrict__ rho,
                                                  double* __restrict__ u, const ChunkDesc* __restrict__ chunks,
                                                  const BoxDesc* __restrict__ boxes, long long nsites)
@@ -91,7 +133,7 @@ __global__ __launch_bounds__(256) void k_moments(const S* __restrict__ src, doub
     for (int k = threadIdx.x; k < ch.count; k += blockDim.x) {
         const long long s = ch.start + k;
         double d, j[3];
-        site_moments<L, S>(base + site_elem(s - b.offset, b.nx, L::Q), b.nx, d, j);
+        stored_site_moments<L, S, SWAPPED>(base, s - b.offset, b, d, j);
         const double r = 1.0 + d;
         rho[s] = r;
 #pragma unroll
@@ -126,7 +168,7 @@ __device__ __forceinline__ void block_tree(double (&acc)[NV], const bool (&is_ma
     for (int k = 0; k < NV; ++k) acc[k] = sh[k][0];
 }
 
-template <class L, class S>
+template <class L, class S, bool SWAPPED>
 __global__ __launch_bounds__(kRedBlock) void k_totals_partial(const S* __restrict__ src,
                                                               const ChunkDesc* __restrict__ chunks,
                                                               const BoxDesc* __restrict__ boxes,
@@ -138,7 +180,7 @@ __global__ __launch_bounds__(kRedBlock) void k_totals_partial(const S* __restric
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int k = threadIdx.x; k < ch.count; k += kRedBlock) {
         double d, j[3];
-        site_moments<L, S>(base + site_elem(ch.start + k - b.offset, b.nx, L::Q), b.nx, d, j);
+        stored_site_moments<L, S, SWAPPED>(base, ch.start + k - b.offset, b, d, j);
         acc[0] += d;
         acc[1] += j[0];
         acc[2] += j[1];
@@ -171,7 +213,7 @@ __global__ __launch_bounds__(kRedBlock) void k_totals_final(const double* __rest
         for (int k = 0; k < 4; ++k) out[b * 4 + k] = acc[k];
 }
 
-template <class L, class S>
+template <class L, class S, bool SWAPPED>
 __global__ __launch_bounds__(kRedBlock) void k_residual_partial(const S* __restrict__ src,
                                                                 const double* __restrict__ rho_ref,
                                                                 const double* __restrict__ u_ref,
@@ -186,7 +228,7 @@ __global__ __launch_bounds__(kRedBlock) void k_residual_partial(const S* __restr
     for (int k = threadIdx.x; k < ch.count; k += kRedBlock) {
         const long long s = ch.start + k;
         double d, j[3];
-        site_moments<L, S>(base + site_elem(s - b.offset, b.nx, L::Q), b.nx, d, j);
+        stored_site_moments<L, S, SWAPPED>(base, s - b.offset, b, d, j);
         const double r = 1.0 + d;
 #pragma unroll
         for (int a = 0; a < L::D; ++a) {
@@ -244,25 +286,33 @@ hipError_t launch_init(int lat, int dtype, int K, const double* rho, const doubl
     });
 }
 
-hipError_t launch_moments(int lat, int dtype, const void* src, double* rho, double* u, const ChunkDesc* chunks,
-                          int nchunks, const BoxDesc* boxes, long long nsites, hipStream_t s)
+hipError_t launch_moments(int lat, int dtype, const void* src, bool swapped, double* rho, double* u,
+                          const ChunkDesc* chunks, int nchunks, const BoxDesc* boxes, long long nsites, hipStream_t s)
 {
     return dispatch_ld(lat, dtype, [&](auto Lt, auto* Sp, auto) -> hipError_t {
         using L = decltype(Lt);
         using S = std::remove_pointer_t<decltype(Sp)>;
-        k_moments<L, S><<<nchunks, 256, 0, s>>>(static_cast<const S*>(src), rho, u, chunks, boxes, nsites);
+        if (swapped)
+            k_moments<L, S, true><<<nchunks, 256, 0, s>>>(static_cast<const S*>(src), rho, u, chunks, boxes, nsites);
+        else
+            k_moments<L, S, false><<<nchunks, 256, 0, s>>>(static_cast<const S*>(src), rho, u, chunks, boxes, nsites);
         return hipGetLastError();
     });
 }
 
-hipError_t launch_totals(int lat, int dtype, const void* src, const ChunkDesc* chunks, int nchunks,
+hipError_t launch_totals(int lat, int dtype, const void* src, bool swapped, const ChunkDesc* chunks, int nchunks,
                          const int* box_chunk_begin, int nbox, const BoxDesc* boxes, double* partial, double* out,
                          hipStream_t s)
 {
     return dispatch_ld(lat, dtype, [&](auto Lt, auto* Sp, auto) -> hipError_t {
         using L = decltype(Lt);
         using S = std::remove_pointer_t<decltype(Sp)>;
-        k_totals_partial<L, S><<<nchunks, kRedBlock, 0, s>>>(static_cast<const S*>(src), chunks, boxes, partial);
+        if (swapped)
+            k_totals_partial<L, S, true><<<nchunks, kRedBlock, 0, s>>>(static_cast<const S*>(src), chunks, boxes,
+                                                                       partial);
+        else
+            k_totals_partial<L, S, false><<<nchunks, kRedBlock, 0, s>>>(static_cast<const S*>(src), chunks, boxes,
+                                                                        partial);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         k_totals_final<<<nbox, kRedBlock, 0, s>>>(partial, box_chunk_begin, out);
@@ -270,15 +320,19 @@ hipError_t launch_totals(int lat, int dtype, const void* src, const ChunkDesc* c
     });
 }
 
-hipError_t launch_residual(int lat, int dtype, const void* src, const double* rho_ref, const double* u_ref,
-                           const ChunkDesc* chunks, int nchunks, const BoxDesc* boxes, long long nsites,
-                           double* partial, double* out, hipStream_t s)
+hipError_t launch_residual(int lat, int dtype, const void* src, bool swapped, const double* rho_ref,
+                           const double* u_ref, const ChunkDesc* chunks, int nchunks, const BoxDesc* boxes,
+                           long long nsites, double* partial, double* out, hipStream_t s)
 {
     return dispatch_ld(lat, dtype, [&](auto Lt, auto* Sp, auto) -> hipError_t {
         using L = decltype(Lt);
         using S = std::remove_pointer_t<decltype(Sp)>;
-        k_residual_partial<L, S><<<nchunks, kRedBlock, 0, s>>>(static_cast<const S*>(src), rho_ref, u_ref, chunks,
-                                                               boxes, nsites, partial);
+        if (swapped)
+            k_residual_partial<L, S, true><<<nchunks, kRedBlock, 0, s>>>(static_cast<const S*>(src), rho_ref, u_ref,
+                                                                         chunks, boxes, nsites, partial);
+        else
+            k_residual_partial<L, S, false><<<nchunks, kRedBlock, 0, s>>>(static_cast<const S*>(src), rho_ref, u_ref,
+                                                                          chunks, boxes, nsites, partial);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         k_residual_final<<<1, kRedBlock, 0, s>>>(partial, nchunks, out);
@@ -319,8 +373,10 @@ __global__ __launch_bounds__(256) void k_unswap(const S* __restrict__ src, S* __
         constexpr int j = decltype(J)::value;
         constexpr int cx = L::c[j][0], cy = L::c[j][1], cz = L::c[j][2];
         const int row = zw[RR + cz] * geo.ny + yw[RR + cy];
-        const S* p = src + row * tile + (long long)mem_row<L>(opp(j)) * geo.nx;
-        q[(long long)mem_row<L>(j) * geo.nx + x] = p[xw[RR + cx]];
+        constexpr int m_src = mem_row<L>(opp(j));
+        constexpr int m_dst = mem_row<L>(j);
+        const S* p = src + row * tile + (long long)m_src * geo.nx;
+        q[(long long)m_dst * geo.nx + x] = p[xw[RR + cx]];
     });
 }
 
@@ -417,9 +473,11 @@ static void fill_info(LatticeInfo* out)
     out->T0 = L::T0;
     out->c.resize(L::Q * 3);
     out->w.resize(L::Q);
+    out->mrow.resize(L::Q);
     for (int i = 0; i < L::Q; ++i) {
         for (int a = 0; a < 3; ++a) out->c[i * 3 + a] = L::c[i][a];
         out->w[i] = L::w[i];
+        out->mrow[i] = mem_row<L>(i);
     }
 }
 

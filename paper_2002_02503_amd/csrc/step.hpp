@@ -55,7 +55,8 @@ __global__ __launch_bounds__(256) void k_step(const S* __restrict__ src, S* __re
     S* q = dst + (long long)(z * geo.ny + y) * tile;
     unroll<L::Q>([&](auto M) {
         constexpr int m = decltype(M)::value;
-        ST::put_nt(at32(q + (long long)m * geo.nx, unsigned(x)), g[mem_pop<L>(m)]);
+        constexpr int i = mem_pop<L>(m);  // a constant expression: the array index must fold
+        ST::put_nt(at32(q + (long long)m * geo.nx, unsigned(x)), g[i]);
     });
 }
 
@@ -117,7 +118,8 @@ __global__ __launch_bounds__(256) void k_step_ip(S* __restrict__ buf, StepGeom g
         collide_site<L, K, KIND, PROJ, R>(g, omega, theta);
         unroll<L::Q>([&](auto M) {
             constexpr int i = mem_pop<L>(decltype(M)::value);
-            const R v = g[opp(i)];
+            constexpr int io = opp(i);
+            const R v = g[io];
             if constexpr (L::c[i][0] == 0) ST::put_nt(elem(M), v);
             else ST::put(elem(M), v);
         });
@@ -125,12 +127,14 @@ __global__ __launch_bounds__(256) void k_step_ip(S* __restrict__ buf, StepGeom g
         S* q = buf + (long long)(z * geo.ny + y) * tile;
         unroll<L::Q>([&](auto M) {
             constexpr int m = decltype(M)::value;
-            g[opp(mem_pop<L>(m))] = ST::get_nt(at32(q + (long long)m * geo.nx, unsigned(x)));
+            constexpr int i = opp(mem_pop<L>(m));
+            g[i] = ST::get_nt(at32(q + (long long)m * geo.nx, unsigned(x)));
         });
         collide_site<L, K, KIND, PROJ, R>(g, omega, theta);
         unroll<L::Q>([&](auto M) {
             constexpr int m = decltype(M)::value;
-            ST::put_nt(at32(q + (long long)m * geo.nx, unsigned(x)), g[mem_pop<L>(m)]);
+            constexpr int i = mem_pop<L>(m);
+            ST::put_nt(at32(q + (long long)m * geo.nx, unsigned(x)), g[i]);
         });
     }
 }

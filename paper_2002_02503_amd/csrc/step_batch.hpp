@@ -75,7 +75,8 @@ __global__ __launch_bounds__(256) void k_step_batch(const S* __restrict__ src, S
         const int out_off = (z * b.ny + y) * tq + x;
         unroll<L::Q>([&](auto M) {
             constexpr int m = decltype(M)::value;
-            ST::put_nt(at32(db, unsigned(out_off + m * b.nx)), g[mem_pop<L>(m)]);
+            constexpr int i = mem_pop<L>(m);  // a constant expression: the array index must fold
+            ST::put_nt(at32(db, unsigned(out_off + m * b.nx)), g[i]);
         });
     }
 }

@@ -132,3 +132,34 @@ def test_tuning_across_layouts_keeps_the_state():
         sim.step(10)
         r, uu = sim.moments()
     assert np.array_equal(r, ref[0]) and np.array_equal(uu, ref[1])
+
+
+def test_in_place_holds_one_buffer():
+    """With library-owned memory the in-place step allocates one population
+    buffer; reading at odd times (moments, totals, residual, checkpoint) needs
+    no second one, and the results equal the two-buffer step's."""
+    import torch
+
+    from paper_2002_02503_amd import lbm
+
+    dims = (128, 128, 64)  # 128^2 * 64 * 19 * 4 B = 80 MiB per buffer
+    rho, u = _fields(3, dims, seed=12, amp=0.03)
+    ref = run_gpu("D3Q19", dims, 0.6, "fp32", rho, u, 9, kernel="scalar")
+    with lbm.Simulation("D3Q19", dims, 0.6, dtype="fp32", kernel="in_place", torch_memory=False) as sim:
+        nbytes = sim.info()["state_bytes"]
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
+        sim.init(rho, u).step(9)
+        r, uu = sim.moments()
+        tot = sim.totals()
+        ck = sim.get_state()
+        torch.cuda.synchronize()
+        used = free0 - torch.cuda.mem_get_info()[0]
+        print(f"in-place: {used / 2**20:.1f} MiB allocated for a {nbytes / 2**20:.1f} MiB state", flush=True)
+        assert used < 1.5 * nbytes
+    assert np.array_equal(r, ref[0]) and np.array_equal(uu, ref[1])
+    with lbm.Simulation("D3Q19", dims, 0.6, dtype="fp32", kernel="scalar") as other:
+        other.set_state(ck)
+        assert np.array_equal(other.totals(), tot)
+        r2, u2 = other.moments()
+        assert np.array_equal(r2, ref[0]) and np.array_equal(u2, ref[1])
