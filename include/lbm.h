@@ -87,7 +87,7 @@ typedef struct {
     int64_t t;                   /* steps taken since lbm_init */
     int64_t bytes_per_site_update; /* 2 * Q * sizeof(storage): one read + one write per population */
     uint64_t state_bytes;        /* bytes of one population buffer (see lbm_state_bytes) */
-    int32_t block, grid;         /* launch shape in use (threads per block; batched grid size, 0 = one block per tile) */
+    int32_t block, grid;         /* launch shape in use (threads per block; batched grid size, 0 = one wave per tile) */
     int32_t graph_chunk;         /* steps per captured graph */
     int32_t kernel;              /* step kernel in use (lbm_kernel, never AUTO) */
     int32_t collision;           /* lbm_collision in use */
@@ -167,8 +167,10 @@ lbm_status lbm_prepare(lbm_t h);
 lbm_status lbm_set_graph_chunk(lbm_t h, int32_t steps);
 
 /* Launch shape: threads per block (64, 128 or 256; 0 = default) and,
- * for batches, the number of blocks of the persistent step kernel (0 = one
- * block per tile).  Only before lbm_init. */
+ * for batches, the number of blocks of the persistent step kernel (0 = enough
+ * blocks for every tile to get its own wave; a batch tile is one wave's work:
+ * whole x-rows of one plane with rows * nx <= 64, or 64 sites of a longer
+ * row).  Only before lbm_init. */
 lbm_status lbm_set_launch(lbm_t h, int32_t block, int32_t grid);
 
 /* Choose the single-box step kernel.  All variants compute the same bits.
@@ -188,7 +190,7 @@ lbm_status lbm_set_kernel(lbm_t h, int32_t kernel);
 /* Autotune the step's launch: time every candidate (single box: the scalar
  * step at 64/128/256 threads per block, the in-place step at 256, and the
  * row-wave step where it applies; batch: 64/128/256 threads x grids of one
- * block per tile or 1024/2048/4096 persistent blocks) over `steps` steps with
+ * wave per tile or 1024/2048/4096 persistent blocks) over `steps` steps with
  * HIP events, in three interleaved rounds, and keep the candidate with the
  * fastest round.  The state is saved before and restored after, so t and
  * the populations are unchanged (all candidates compute the same bits).

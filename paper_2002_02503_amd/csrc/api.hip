@@ -96,7 +96,6 @@ struct lbm_ctx {
     // batched step tables
     TileDesc* d_tiles = nullptr;
     int ntiles = 0;
-    int tiles_block = 0;
     BoxDesc* d_boxes = nullptr;
     // reductions
     ChunkDesc* d_chunks = nullptr;
@@ -216,10 +215,14 @@ lbm_status device_check(int* dev)
     return LBM_OK;
 }
 
-lbm_status build_tiles(lbm_ctx* h, int block)
+// Wave tiles of the batched step (step_batch.hpp): whole x-rows of one plane
+// with rows * nx <= 64, or 64-site pieces of a row when nx > 64.  The table
+// does not depend on the block size.
+lbm_status build_tiles(lbm_ctx* h)
 {
+    constexpr int kWave = 64;
     if (is_single(h)) return LBM_OK;
-    if (h->d_tiles && h->tiles_block == block) return LBM_OK;
+    if (h->d_tiles) return LBM_OK;
     std::vector<TileDesc> tiles;
     for (int b = 0; b < h->nbox; ++b) {
         const int nx = int(h->dims[3 * b]), ny = int(h->dims[3 * b + 1]), nz = int(h->dims[3 * b + 2]);
@@ -233,8 +236,8 @@ lbm_status build_tiles(lbm_ctx* h, int block)
         t.box = b;
         for (int z = 0; z < nz; ++z) {
             t.z = z;
-            if (nx <= block) {
-                const int per = block / nx;  // whole rows per tile
+            if (nx <= kWave) {
+                const int per = kWave / nx;  // whole rows per tile
                 for (int y = 0; y < ny; y += per) {
                     t.y0 = y;
                     t.rows = (ny - y < per) ? ny - y : per;
@@ -243,7 +246,7 @@ lbm_status build_tiles(lbm_ctx* h, int block)
                 }
             } else {
                 for (int y = 0; y < ny; ++y)
-                    for (int x0 = 0; x0 < nx; x0 += block) {
+                    for (int x0 = 0; x0 < nx; x0 += kWave) {
                         t.y0 = y;
                         t.rows = 1;
                         t.x0 = x0;
@@ -252,13 +255,10 @@ lbm_status build_tiles(lbm_ctx* h, int block)
             }
         }
     }
-    (void)hipFree(h->d_tiles);
-    h->d_tiles = nullptr;
     HIP_TRY(hipMalloc(&h->d_tiles, tiles.size() * sizeof(TileDesc)), "hipMalloc(tiles)");
     HIP_TRY(hipMemcpy(h->d_tiles, tiles.data(), tiles.size() * sizeof(TileDesc), hipMemcpyHostToDevice),
             "copy tiles");
     h->ntiles = int(tiles.size());
-    h->tiles_block = block;
     drop_graphs(h);
     return LBM_OK;
 }
@@ -355,7 +355,6 @@ lbm_status create_common(lbm_t* out, int32_t lattice, int32_t nbox, const int64_
             boxes[b].nx = int(dims[3 * b]);
             boxes[b].ny = int(dims[3 * b + 1]);
             boxes[b].nz = int(dims[3 * b + 2]);
-            boxes[b].inv_nx = float(1.0 / double(dims[3 * b]));
             boxes[b].offset = h->offset[b];
             boxes[b].omega = 1.0 - 1.0 / tau[b];
         }
@@ -502,7 +501,7 @@ lbm_status build_graph(lbm_ctx* h, int parity)
         (void)hipGraphExecDestroy(h->gexec[parity]);
         h->gexec[parity] = nullptr;
     }
-    lbm_status st = build_tiles(h, effective_block(h));
+    lbm_status st = build_tiles(h);
     if (st != LBM_OK) return st;
     HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
     hipError_t le = hipSuccess;
@@ -660,7 +659,7 @@ lbm_status lbm_init(lbm_t h, const double* rho, const double* u, int32_t on_devi
     if (!rho || !u) return fail(LBM_EINVAL, "rho or u is NULL");
     HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
     if (lbm_status st = ensure_buffers(h)) return st;
-    if (lbm_status st = build_tiles(h, effective_block(h))) return st;
+    if (lbm_status st = build_tiles(h)) return st;
     const size_t n = size_t(h->nsites);
     double *drho = nullptr, *du = nullptr;
     bool t1 = false, t2 = false;
@@ -703,7 +702,7 @@ lbm_status lbm_step(lbm_t h, int64_t n)
     HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
     if (!in_place(h))
         if (lbm_status st = ensure_second(h)) return st;
-    if (lbm_status st = build_tiles(h, effective_block(h))) return st;
+    if (lbm_status st = build_tiles(h)) return st;
     const int G = h->graph_chunk;
     int64_t left = n;
     if (G > 1) {
@@ -1013,7 +1012,7 @@ lbm_status lbm_set_state(lbm_t h, const void* buf, size_t bytes)
         return fail(LBM_EINVAL, "checkpoint does not match this handle (lattice, dtype, K or geometry)");
     HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
     if (lbm_status st = ensure_buffers(h)) return st;
-    if (lbm_status st = build_tiles(h, effective_block(h))) return st;
+    if (lbm_status st = build_tiles(h)) return st;
     const char* src = static_cast<const char*>(buf) + sizeof(hd);
     HIP_TRY(hipMemcpyAsync(h->buf[0], src, size_t(h->lat.Q) * size_t(h->nsites) * h->elem, hipMemcpyHostToDevice,
                            h->stream),

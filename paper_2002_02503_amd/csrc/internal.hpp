@@ -36,9 +36,9 @@ struct VecGeom {
     int nrows;            // ny * nz
 };
 
-// A tile of the batched step: in box `box`, plane z, the x-rows y0 .. y0 +
-// rows - 1 (rows * nx <= threads per block), or, when nx exceeds the block,
-// the single row y0 from x0 on.  The tile carries its box's geometry, first
+// A tile of the batched step, one wavefront's work: in box `box`, plane z,
+// the x-rows y0 .. y0 + rows - 1 (rows * nx <= 64), or, when nx exceeds 64,
+// the 64 sites of row y0 from x0 on.  The tile carries its box's geometry, first
 // site and relaxation factor, so a block starts after one 64-byte scalar load.
 struct alignas(64) TileDesc {
     int z, y0, rows, x0;
@@ -52,7 +52,6 @@ static_assert(sizeof(TileDesc) == 64, "tile descriptor is one scalar load");
 
 struct BoxDesc {
     int nx, ny, nz;
-    float inv_nx;         // 1 / nx, for the lane -> (row, x) split of a tile
     long long offset;     // O_b: global index of the box's first site
     double omega;         // 1 - 1/tau
 };

@@ -9,12 +9,18 @@
 namespace lbm {
 
 // ---------------------------------------------------------------------------
-// Fused step, batch of boxes.  A tile is a run of whole x-rows of one z-plane
-// of one box (or a block-wide piece of one row when nx exceeds the block), so
-// z and the box are uniform and each lane finds its row with one exact
-// reciprocal multiply.  A fixed grid walks the tile table (grid-stride): one
-// launch advances every box by one step, each with its own tau.  Offsets
-// inside a box fit 32 bits (checked on the host).
+// Fused step, batch of boxes.  A tile is one wavefront's work: whole x-rows of
+// one z-plane of one box (rows * nx <= 64), or a 64-site piece of one row when
+// nx exceeds 64.  The box and z are uniform over the wave, so each wave reads
+// its tile descriptor with one scalar load, and each lane finds its row with
+// one exact reciprocal multiply.  Every row tile (all populations of one
+// x-row) is written by one wave: measured, tiles that split rows between
+// waves (flat 64-site runs, or rows spread over the waves of a block) leave
+// partly written cache lines in every population row and run at half the
+// bandwidth.  A block of W waves takes W consecutive tiles; a fixed grid walks
+// the tile table (grid-stride).  One launch advances every box by one step,
+// each with its own tau.  Offsets inside a box fit 32 bits (checked on the
+// host).
 // ---------------------------------------------------------------------------
 
 template <class L, class S, int K, int KIND>
@@ -27,11 +33,13 @@ __global__ __launch_bounds__(256) void k_step_batch(const S* __restrict__ src, S
     constexpr bool PROJ = !std::is_same<R, double>::value;
     constexpr int RR = L::R;
 
-    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int waves = int(blockDim.x) >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);  // uniform: scalar descriptor loads
+    const int tid = int(threadIdx.x) & 63;
+    for (int t = int(blockIdx.x) * waves + wave; t < ntiles; t += int(gridDim.x) * waves) {
         const TileDesc b = tiles[t];
-        const int tid = int(threadIdx.x);
         int r, x;
-        if (b.nx <= int(blockDim.x)) {
+        if (b.nx <= 64) {
             // (tid + 1/2) / nx is at least 1/(2 nx) away from an integer, far
             // more than the float rounding of the product: the floor is exact
             r = int((float(tid) + 0.5f) * b.inv_nx);
@@ -89,7 +97,9 @@ hipError_t launch_step_batch_l(int K, int kind, const void* src, void* dst, cons
         using R = typename Store<S>::R;
         constexpr int KK = decltype(Kc)::value;
         constexpr int KD = decltype(Kind)::value;
-        const int g = (grid > 0 && grid < ntiles) ? grid : ntiles;
+        const int waves = block / 64;
+        const int need = (ntiles + waves - 1) / waves;  // blocks that give every tile its own wave
+        const int g = (grid > 0 && grid < need) ? grid : need;
         k_step_batch<L, S, KK, KD><<<g, block, 0, s>>>(static_cast<const S*>(src), static_cast<S*>(dst), tiles,
                                                        ntiles, R(theta));
         return hipGetLastError();
