@@ -72,9 +72,11 @@ typedef enum {
     LBM_KERNEL_AUTO = 0,      /* the scalar step unless a tuned choice was set */
     LBM_KERNEL_SCALAR = 1,    /* one site per thread, 4/8-byte accesses */
     LBM_KERNEL_ROW_WAVE = 2,  /* V sites per lane, 8/16-byte accesses, x-neighbours by lane shuffle */
-    LBM_KERNEL_IN_PLACE = 3   /* one site per thread on one buffer: each step reads and writes the same
+    LBM_KERNEL_IN_PLACE = 3,  /* one site per thread on one buffer: each step reads and writes the same
                                  elements, alternating between two layouts of the state (bit-identical
                                  results, half the memory) */
+    LBM_KERNEL_TWO_ROW = 4    /* two sites per thread (rows 2j and 2j+1, ny even): the second site's loads
+                                 are in flight while the first collides (bit-identical results) */
 } lbm_kernel;
 
 typedef struct {
@@ -184,12 +186,13 @@ lbm_status lbm_set_launch(lbm_t h, int32_t block, int32_t grid);
  * moments, totals and residual read it as it is, and lbm_get_state returns the
  * natural layout (rearranged on the host).  Switching kernels later (lbm_tune)
  * allocates the second buffer.  Batches always use the tiled batched kernel.
+ * LBM_KERNEL_TWO_ROW needs a single box with ny even (else LBM_EINVAL).
  * Only before lbm_init. */
 lbm_status lbm_set_kernel(lbm_t h, int32_t kernel);
 
 /* Autotune the step's launch: time every candidate (single box: the scalar
- * step at 64/128/256 threads per block, the in-place step at 256, and the
- * row-wave step where it applies; batch: 64/128/256 threads x grids of one
+ * step at 64/128/256 threads per block, the in-place step and the two-row
+ * step (ny even) at 256, and the row-wave step where it applies; batch: 64/128/256 threads x grids of one
  * wave per tile or 1024/2048/4096 persistent blocks) over `steps` steps with
  * HIP events, in three interleaved rounds, and keep the candidate with the
  * fastest round.  The state is saved before and restored after, so t and

@@ -434,7 +434,7 @@ hipError_t launch_one(lbm_ctx* h, int parity, hipStream_t s)
     }
     if (is_single(h))
         return launch_step(h->lattice, h->dtype, h->K, step_kind(h), src, dst, single_geom(h, block),
-                           1.0 - 1.0 / h->tau[0], h->theta, block, s);
+                           1.0 - 1.0 / h->tau[0], h->theta, block, effective_kernel(h) == LBM_KERNEL_TWO_ROW, s);
     return launch_step_batch(h->lattice, h->dtype, h->K, step_kind(h), src, dst, h->d_tiles, h->ntiles, h->theta,
                              block, h->grid, s);
 }
@@ -641,10 +641,12 @@ lbm_status lbm_set_kernel(lbm_t h, int32_t kernel)
 {
     if (lbm_status st = check_handle(h)) return st;
     if (kernel != LBM_KERNEL_AUTO && kernel != LBM_KERNEL_SCALAR && kernel != LBM_KERNEL_ROW_WAVE &&
-        kernel != LBM_KERNEL_IN_PLACE)
+        kernel != LBM_KERNEL_IN_PLACE && kernel != LBM_KERNEL_TWO_ROW)
         return fail(LBM_EINVAL, "unknown kernel variant %d", kernel);
     if (kernel == LBM_KERNEL_IN_PLACE && !is_single(h))
         return fail(LBM_EINVAL, "the in-place step is for a single box; batches use the tiled batched kernel");
+    if (kernel == LBM_KERNEL_TWO_ROW && (!is_single(h) || h->dims[1] % 2 != 0))
+        return fail(LBM_EINVAL, "the two-row step needs a single box with ny even");
     if (kernel == LBM_KERNEL_ROW_WAVE && !row_wave_sites(h))
         return fail(LBM_EINVAL, "the row-wave step needs a single box with nx a multiple of the sites per lane "
                                 "and at most 64 lanes per row");
@@ -793,6 +795,8 @@ lbm_status lbm_tune(lbm_t h, int32_t steps, const char* cache_path)
     if (cache_lookup(cache_path, key, &best)) {
         if (best.kernel == LBM_KERNEL_ROW_WAVE && !row_wave_sites(h)) best.kernel = LBM_KERNEL_SCALAR;
         if (best.kernel == LBM_KERNEL_IN_PLACE && !is_single(h)) best.kernel = LBM_KERNEL_SCALAR;
+        if (best.kernel == LBM_KERNEL_TWO_ROW && (!is_single(h) || h->dims[1] % 2 != 0))
+            best.kernel = LBM_KERNEL_SCALAR;
         return apply_choice(h, best);
     }
     HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
@@ -801,6 +805,7 @@ lbm_status lbm_tune(lbm_t h, int32_t steps, const char* cache_path)
     if (is_single(h)) {
         for (int b : {64, 128, 256}) cand.push_back({LBM_KERNEL_SCALAR, b, 0});
         cand.push_back({LBM_KERNEL_IN_PLACE, 256, 0});
+        if (h->dims[1] % 2 == 0) cand.push_back({LBM_KERNEL_TWO_ROW, 256, 0});
         if (row_wave_sites(h)) cand.push_back({LBM_KERNEL_ROW_WAVE, 0, 0});
     } else {
         for (int b : {64, 128, 256})

@@ -70,8 +70,9 @@ hipError_t launch_init(int lat, int dtype, int K, const double* rho, const doubl
                        hipStream_t s);
 // The fused step.  kind: collision kind (collide.hpp: 0 filtered, 1 BGK,
 // 2 filtered with the energy-flux term of weight theta).
+// pair: two sites per thread (rows 2j, 2j + 1; ny even).
 hipError_t launch_step(int lat, int dtype, int K, int kind, const void* src, void* dst, const StepGeom& geo,
-                       double omega, double theta, int block, hipStream_t s);
+                       double omega, double theta, int block, bool pair, hipStream_t s);
 // The in-place step on one buffer: from the natural layout to the swapped one
 // (from_natural) or back (step.hpp, k_step_ip).
 hipError_t launch_step_ip(int lat, int dtype, int K, int kind, void* buf, bool from_natural, const StepGeom& geo,

@@ -406,12 +406,12 @@ static hipError_t by_pair(int lat, int dtype, F&& f)
 }
 
 hipError_t launch_step(int lat, int dtype, int K, int kind, const void* src, void* dst, const StepGeom& geo,
-                       double omega, double theta, int block, hipStream_t s)
+                       double omega, double theta, int block, bool pair, hipStream_t s)
 {
     return by_pair(lat, dtype, [&](auto Lt, auto* Sp) {
         using L = decltype(Lt);
         using S = std::remove_pointer_t<decltype(Sp)>;
-        return launch_step_l<L, S>(K, kind, src, dst, geo, omega, theta, block, s);
+        return launch_step_l<L, S>(K, kind, src, dst, geo, omega, theta, block, pair, s);
     });
 }
 

@@ -61,6 +61,64 @@ __global__ __launch_bounds__(256) void k_step(const S* __restrict__ src, S* __re
 }
 
 // ---------------------------------------------------------------------------
+// Fused step, single box, two sites per thread: the sites at x of the rows
+// y0 = 2 blockIdx.y and y0 + 1 (ny even).  Both sites' populations are loaded
+// before the first site collides, so while one site computes, the other's
+// loads are in flight; the in-order memory counter lets the second site's
+// loads complete while the first site's stores are still outstanding.  The
+// per-site arithmetic is that of k_step (the same bits).
+// ---------------------------------------------------------------------------
+
+template <class L, class S, int K, int KIND>
+__global__ __launch_bounds__(256) void k_step_pair(const S* __restrict__ src, S* __restrict__ dst, StepGeom geo,
+                                                   typename Store<S>::R omega, typename Store<S>::R theta)
+{
+    using ST = Store<S>;
+    using R = typename ST::R;
+    constexpr bool PROJ = !std::is_same<R, double>::value;
+    constexpr int RR = L::R;
+
+    const int y0 = 2 * int(blockIdx.y);
+    const int z = blockIdx.z;
+    const int x = int(blockIdx.x) * int(blockDim.x) + int(threadIdx.x);
+    if (x >= geo.nx) return;
+    const long long tile = (long long)L::Q * geo.nx;
+
+    // yw[k] = y0 + k - RR for k = 0 .. 2 RR + 1 (both rows' neighbourhoods)
+    int xw[2 * RR + 1], yw[2 * RR + 2], zw[2 * RR + 1];
+#pragma unroll
+    for (int k = 0; k <= 2 * RR; ++k) {
+        xw[k] = wrap_coord(x + k - RR, geo.nx);
+        zw[k] = wrap_coord(z + k - RR, geo.nz);
+    }
+#pragma unroll
+    for (int k = 0; k <= 2 * RR + 1; ++k) yw[k] = wrap_coord(y0 + k - RR, geo.ny);
+
+    R g[2][L::Q];
+    unroll<2>([&](auto Sj) {
+        constexpr int sj = decltype(Sj)::value;
+        unroll<L::Q>([&](auto M) {  // in tile-row order
+            constexpr int m = decltype(M)::value;
+            constexpr int i = mem_pop<L>(m);
+            constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
+            const int row = zw[RR - cz] * geo.ny + yw[sj + RR - cy];
+            const S* p = src + row * tile + (long long)m * geo.nx;
+            g[sj][i] = load_population<ST, cx>(at32(p, unsigned(xw[RR - cx])));
+        });
+    });
+    unroll<2>([&](auto Sj) {
+        constexpr int sj = decltype(Sj)::value;
+        collide_site<L, K, KIND, PROJ, R>(g[sj], omega, theta);
+        S* q = dst + (long long)(z * geo.ny + y0 + sj) * tile;
+        unroll<L::Q>([&](auto M) {
+            constexpr int m = decltype(M)::value;
+            constexpr int i = mem_pop<L>(m);
+            ST::put_nt(at32(q + (long long)m * geo.nx, unsigned(x)), g[sj][i]);
+        });
+    });
+}
+
+// ---------------------------------------------------------------------------
 // Fused step, single box, in place: one buffer, two alternating forms.
 // The state is in one of two layouts:
 //   natural: tile row m(i) of site x holds the post-collision population i of
@@ -217,14 +275,21 @@ __global__ __launch_bounds__(256) void k_step_vec(const S* __restrict__ src, S* 
 
 template <class L, class S>
 hipError_t launch_step_l(int K, int kind, const void* src, void* dst, const StepGeom& geo, double omega,
-                         double theta, int block, hipStream_t s)
+                         double theta, int block, bool pair, hipStream_t s)
 {
     return dispatch_pair<L, S>(K, kind, [&](auto, auto*, auto Kc, auto Kind) -> hipError_t {
         using R = typename Store<S>::R;
         constexpr int KK = decltype(Kc)::value;
         constexpr int KD = decltype(Kind)::value;
-        k_step<L, S, KK, KD><<<dim3(unsigned(geo.xblocks), unsigned(geo.ny), unsigned(geo.nz)), block, 0, s>>>(
-            static_cast<const S*>(src), static_cast<S*>(dst), geo, R(omega), R(theta));
+        if (pair) {
+            if (geo.ny % 2 != 0) return hipErrorInvalidValue;
+            k_step_pair<L, S, KK, KD>
+                <<<dim3(unsigned(geo.xblocks), unsigned(geo.ny / 2), unsigned(geo.nz)), block, 0, s>>>(
+                    static_cast<const S*>(src), static_cast<S*>(dst), geo, R(omega), R(theta));
+        } else {
+            k_step<L, S, KK, KD><<<dim3(unsigned(geo.xblocks), unsigned(geo.ny), unsigned(geo.nz)), block, 0, s>>>(
+                static_cast<const S*>(src), static_cast<S*>(dst), geo, R(omega), R(theta));
+        }
         return hipGetLastError();
     });
 }

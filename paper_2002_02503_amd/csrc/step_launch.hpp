@@ -12,10 +12,12 @@ namespace lbm {
 
 struct bf16_t;
 
-// Single box, one site per thread: grid (xblocks, ny, nz) of `block` threads.
+// Single box, one site per thread: grid (xblocks, ny, nz) of `block` threads;
+// pair: two sites per thread in rows 2j and 2j + 1 (ny even), grid
+// (xblocks, ny / 2, nz).
 template <class L, class S>
 hipError_t launch_step_l(int K, int kind, const void* src, void* dst, const StepGeom& geo, double omega,
-                         double theta, int block, hipStream_t s);
+                         double theta, int block, bool pair, hipStream_t s);
 
 // Single box, in place: from the natural layout to the swapped one
 // (from_natural) or back (see k_step_ip).
@@ -39,7 +41,7 @@ hipError_t launch_step_batch_l(int K, int kind, const void* src, void* dst, cons
 
 #define LBM_DECLARE_STEP_INSTANCES(EXT, L, S)                                                                    \
     EXT template hipError_t launch_step_l<L, S>(int, int, const void*, void*, const StepGeom&, double, double,  \
-                                                int, hipStream_t);                                             \
+                                                int, bool, hipStream_t);                                       \
     EXT template hipError_t launch_step_ip_l<L, S>(int, int, void*, bool, const StepGeom&, double, double, int, \
                                                    hipStream_t);                                               \
     EXT template int vec_sites_l<L, S>();                                                                      \

@@ -163,3 +163,33 @@ def test_in_place_holds_one_buffer():
         assert np.array_equal(other.totals(), tot)
         r2, u2 = other.moments()
         assert np.array_equal(r2, ref[0]) and np.array_equal(u2, ref[1])
+
+
+TWO_ROW_CASES = [
+    ("D3Q19", (256, 6, 4), "fp32", {}),
+    ("D3Q19", (70, 10, 6), "fp16", {"collision": "bgk"}),
+    ("D3Q19", (64, 2, 3), "fp64", {"theta": 0.5}),
+    ("D3Q15", (300, 4, 3), "bf16", {}),
+    ("D2Q9", (300, 8, 1), "fp32", {}),
+    ("D3Q39", (40, 6, 7), "fp32", {"K": 5}),
+    ("D3Q39", (9, 2, 5), "fp32", {}),
+]
+
+
+@pytest.mark.parametrize("lattice,dims,dtype,kw", TWO_ROW_CASES)
+def test_two_row_equals_scalar_step(lattice, dims, dtype, kw):
+    """Two sites per thread (rows 2j and 2j + 1) compute the bits of the
+    one-site step."""
+    D = 2 if lattice == "D2Q9" else 3
+    rho, u = _fields(D, dims, seed=sum(dims) + 1)
+    a = run_gpu(lattice, dims, 0.6, dtype, rho, u, 13, kernel="two_row", **kw)
+    b = run_gpu(lattice, dims, 0.6, dtype, rho, u, 13, kernel="scalar", **kw)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_two_row_needs_even_ny():
+    from paper_2002_02503_amd import lbm
+
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.Simulation("D3Q19", (32, 7, 4), 0.6, kernel="two_row")
+    assert e.value.name == "LBM_EINVAL"
