@@ -190,18 +190,18 @@ lbm_status lbm_set_launch(lbm_t h, int32_t block, int32_t grid);
  * Only before lbm_init. */
 lbm_status lbm_set_kernel(lbm_t h, int32_t kernel);
 
-/* Autotune the step's launch: time every candidate (single box: the scalar
- * step at 64/128/256 threads per block, the in-place step and the two-row
- * step (ny even) at 256, and the row-wave step where it applies; batch: 64/128/256 threads x grids of one
- * wave per tile or 1024/2048/4096 persistent blocks) over `steps` steps with
- * HIP events, in three interleaved rounds, and keep the candidate with the
- * fastest round.  The state is saved before and restored after, so t and
- * the populations are unchanged (all candidates compute the same bits).
- * Choices are appended to the text file `cache_path` (NULL: the path in the
- * environment variable LBM_TUNE_CACHE, or no cache); a later call with the same
- * lattice, dtype, K and geometry reuses the cached choice without timing.
- * Needs an initialised handle (LBM_ESTATE otherwise); allocates one state-sized
- * scratch buffer while timing. */
+/* Autotune the step's launch: time every candidate over `steps` steps with HIP
+ * events, in three interleaved rounds, and keep the candidate with the fastest
+ * round.  Single box: the scalar step at 64/128/256 threads per block, the
+ * in-place step and the two-row step (ny even) at 256, and the row-wave step
+ * where it applies.  Batch: 64/128/256 threads with one wave per tile, or
+ * 1024/2048/4096 persistent blocks.  The state is saved before and restored
+ * after, so t and the populations are unchanged (all candidates compute the
+ * same bits).  Choices are appended to the text file `cache_path` (NULL: the
+ * path in the environment variable LBM_TUNE_CACHE, or no cache); a later call
+ * with the same lattice, dtype, K, collision kind and geometry reuses the
+ * cached choice without timing.  Needs an initialised handle (LBM_ESTATE
+ * otherwise); allocates one state-sized scratch buffer while timing. */
 lbm_status lbm_tune(lbm_t h, int32_t steps, const char* cache_path);
 
 /* rho and u (eq. mme) of the current state, in float64, in the field layout
