@@ -187,7 +187,9 @@ lbm_status lbm_set_launch(lbm_t h, int32_t block, int32_t grid);
  * natural layout (rearranged on the host).  Switching kernels later (lbm_tune)
  * allocates the second buffer.  Batches always use the tiled batched kernel.
  * LBM_KERNEL_TWO_ROW needs a single box with ny even (else LBM_EINVAL).
- * Only before lbm_init. */
+ * May be called at any time: on an initialised handle the state is first
+ * brought to the natural layout (which may allocate the second buffer), and
+ * the run continues bit for bit. */
 lbm_status lbm_set_kernel(lbm_t h, int32_t kernel);
 
 /* Autotune the step's launch: time every candidate over `steps` steps with HIP

@@ -650,6 +650,9 @@ lbm_status lbm_set_kernel(lbm_t h, int32_t kernel)
     if (kernel == LBM_KERNEL_ROW_WAVE && !row_wave_sites(h))
         return fail(LBM_EINVAL, "the row-wave step needs a single box with nx a multiple of the sites per lane "
                                 "and at most 64 lanes per row");
+    // on an initialised handle the state first goes to the natural layout in
+    // buf[0], where every kernel can start
+    if (lbm_status st = canonicalize(h)) return st;
     h->kernel = kernel;
     drop_graphs(h);
     return LBM_OK;

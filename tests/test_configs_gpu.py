@@ -148,6 +148,31 @@ def test_turbulence_256_sampled_parity(turbulence_256, dtype):
     assert eu < BOUND[dtype] and er < BOUND[dtype]
 
 
+@pytest.fixture(scope="module")
+def turbulence_256_samples(turbulence_256):
+    rho, u = turbulence_256
+    pts = sample_points(rho.shape, 48, seed=1)
+    r_ref, u_ref = lightcone_samples("D3Q19", rho, u, 0.51, 3, pts)
+    return pts, r_ref, u_ref
+
+
+@pytest.mark.parametrize("kernel", ["in_place", "two_row"])
+@pytest.mark.parametrize("dtype", ["fp32", "bf16"])
+def test_turbulence_256_sampled_parity_other_kernels(turbulence_256, turbulence_256_samples, kernel, dtype):
+    """The same full-size check for the kernel forms the tuner may pick for the
+    benchmark (after 3 steps the in-place state is in its swapped layout)."""
+    rho, u = turbulence_256
+    pts, r_ref, u_ref = turbulence_256_samples
+    with lbm.Simulation("D3Q19", (256, 256, 256), 0.51, dtype=dtype, kernel=kernel) as sim:
+        sim.init(rho, u).step(3)
+        r, uu = sim.moments()
+    idx = tuple(np.array(pts).T)
+    eu = float(np.abs(uu[(slice(None),) + idx] - u_ref).max() / np.abs(u).max())
+    er = float(np.abs(r[idx] - r_ref).max())
+    print(f"turbulence 256^3 {dtype} {kernel}, 3 steps, sampled: u {eu:.2e} rho {er:.2e}", flush=True)
+    assert eu < BOUND[dtype] and er < BOUND[dtype]
+
+
 def test_turbulence_256_full_horizon_invariants(turbulence_256):
     """500 steps at full size in FP32: global mass and momentum conserved
     (FP64 totals on the GPU), kinetic energy decays monotonically."""
