@@ -67,7 +67,7 @@ typedef enum {
     LBM_COLLISION_BGK = 1        /* eq. BGK, f' = f - (f - f^eq)/tau, with the same truncated f^eq */
 } lbm_collision;
 
-/* Step-kernel variants for a single box (lbm_set_kernel). */
+/* Step-kernel variants (lbm_set_kernel): 1-4 for a single box, 5 for a batch. */
 typedef enum {
     LBM_KERNEL_AUTO = 0,      /* the scalar step unless a tuned choice was set */
     LBM_KERNEL_SCALAR = 1,    /* one site per thread, 4/8-byte accesses */
@@ -75,8 +75,10 @@ typedef enum {
     LBM_KERNEL_IN_PLACE = 3,  /* one site per thread on one buffer: each step reads and writes the same
                                  elements, alternating between two layouts of the state (bit-identical
                                  results, half the memory) */
-    LBM_KERNEL_TWO_ROW = 4    /* two sites per thread (rows 2j and 2j+1, ny even): the second site's loads
+    LBM_KERNEL_TWO_ROW = 4,   /* two sites per thread (rows 2j and 2j+1, ny even): the second site's loads
                                  are in flight while the first collides (bit-identical results) */
+    LBM_KERNEL_STAGED = 5     /* batches only: a tile of whole rows (rows * nx <= 64) collects its outputs in
+                                 LDS and writes them as one contiguous run (bit-identical results) */
 } lbm_kernel;
 
 typedef struct {
@@ -185,7 +187,11 @@ lbm_status lbm_set_launch(lbm_t h, int32_t block, int32_t grid);
  * layout (population i of site x at site x + c_i, tile row m(opp(i))); the
  * moments, totals and residual read it as it is, and lbm_get_state returns the
  * natural layout (rearranged on the host).  Switching kernels later (lbm_tune)
- * allocates the second buffer.  Batches always use the tiled batched kernel.
+ * allocates the second buffer.  Batches always use the tiled batched kernel,
+ * with direct stores (LBM_KERNEL_AUTO, LBM_KERNEL_SCALAR) or staged ones
+ * (LBM_KERNEL_STAGED: rows whose population rows do not fill whole 128-byte
+ * lines are otherwise written as partial lines); the other variants are
+ * LBM_EINVAL for a batch, and LBM_KERNEL_STAGED for a single box.
  * LBM_KERNEL_TWO_ROW needs a single box with ny even (else LBM_EINVAL).
  * May be called at any time: on an initialised handle the state is first
  * brought to the natural layout (which may allocate the second buffer), and
@@ -196,8 +202,9 @@ lbm_status lbm_set_kernel(lbm_t h, int32_t kernel);
  * events, in three interleaved rounds, and keep the candidate with the fastest
  * round.  Single box: the scalar step at 64/128/256 threads per block, the
  * in-place step and the two-row step (ny even) at 256, and the row-wave step
- * where it applies.  Batch: 64/128/256 threads with one wave per tile, or
- * 1024/2048/4096 persistent blocks.  The state is saved before and restored
+ * where it applies.  Batch: the direct-store and staged kernels at 64/128/256
+ * threads with one wave per tile, and the direct-store kernel with
+ * 1024/2048/4096 persistent blocks of 64 threads.  The state is saved before and restored
  * after, so t and the populations are unchanged (all candidates compute the
  * same bits).  Choices are appended to the text file `cache_path` (NULL: the
  * path in the environment variable LBM_TUNE_CACHE, or no cache); a later call

@@ -132,7 +132,7 @@ int step_kind(const lbm_ctx* h)
 
 int effective_kernel(const lbm_ctx* h)
 {
-    if (!is_single(h)) return LBM_KERNEL_SCALAR;
+    if (!is_single(h)) return h->kernel == LBM_KERNEL_STAGED ? LBM_KERNEL_STAGED : LBM_KERNEL_SCALAR;
     if (h->kernel == LBM_KERNEL_AUTO) return LBM_KERNEL_SCALAR;  // measured faster unless tuned otherwise
     return h->kernel;
 }
@@ -436,7 +436,7 @@ hipError_t launch_one(lbm_ctx* h, int parity, hipStream_t s)
         return launch_step(h->lattice, h->dtype, h->K, step_kind(h), src, dst, single_geom(h, block),
                            1.0 - 1.0 / h->tau[0], h->theta, block, effective_kernel(h) == LBM_KERNEL_TWO_ROW, s);
     return launch_step_batch(h->lattice, h->dtype, h->K, step_kind(h), src, dst, h->d_tiles, h->ntiles, h->theta,
-                             block, h->grid, s);
+                             block, h->grid, h->kernel == LBM_KERNEL_STAGED, s);
 }
 
 // Where the current state is, and whether the in-place step left it in the
@@ -641,8 +641,10 @@ lbm_status lbm_set_kernel(lbm_t h, int32_t kernel)
 {
     if (lbm_status st = check_handle(h)) return st;
     if (kernel != LBM_KERNEL_AUTO && kernel != LBM_KERNEL_SCALAR && kernel != LBM_KERNEL_ROW_WAVE &&
-        kernel != LBM_KERNEL_IN_PLACE && kernel != LBM_KERNEL_TWO_ROW)
+        kernel != LBM_KERNEL_IN_PLACE && kernel != LBM_KERNEL_TWO_ROW && kernel != LBM_KERNEL_STAGED)
         return fail(LBM_EINVAL, "unknown kernel variant %d", kernel);
+    if (kernel == LBM_KERNEL_STAGED && is_single(h))
+        return fail(LBM_EINVAL, "the staged step is the batched step's; a single box writes whole rows already");
     if (kernel == LBM_KERNEL_IN_PLACE && !is_single(h))
         return fail(LBM_EINVAL, "the in-place step is for a single box; batches use the tiled batched kernel");
     if (kernel == LBM_KERNEL_TWO_ROW && (!is_single(h) || h->dims[1] % 2 != 0))
@@ -798,6 +800,7 @@ lbm_status lbm_tune(lbm_t h, int32_t steps, const char* cache_path)
     if (cache_lookup(cache_path, key, &best)) {
         if (best.kernel == LBM_KERNEL_ROW_WAVE && !row_wave_sites(h)) best.kernel = LBM_KERNEL_SCALAR;
         if (best.kernel == LBM_KERNEL_IN_PLACE && !is_single(h)) best.kernel = LBM_KERNEL_SCALAR;
+        if (best.kernel == LBM_KERNEL_STAGED && is_single(h)) best.kernel = LBM_KERNEL_SCALAR;
         if (best.kernel == LBM_KERNEL_TWO_ROW && (!is_single(h) || h->dims[1] % 2 != 0))
             best.kernel = LBM_KERNEL_SCALAR;
         return apply_choice(h, best);
@@ -811,8 +814,9 @@ lbm_status lbm_tune(lbm_t h, int32_t steps, const char* cache_path)
         if (h->dims[1] % 2 == 0) cand.push_back({LBM_KERNEL_TWO_ROW, 256, 0});
         if (row_wave_sites(h)) cand.push_back({LBM_KERNEL_ROW_WAVE, 0, 0});
     } else {
-        for (int b : {64, 128, 256})
-            for (int g : {0, 1024, 2048, 4096}) cand.push_back({LBM_KERNEL_SCALAR, b, g});
+        for (int k : {LBM_KERNEL_SCALAR, LBM_KERNEL_STAGED})
+            for (int b : {64, 128, 256}) cand.push_back({k, b, 0});
+        for (int g : {1024, 2048, 4096}) cand.push_back({LBM_KERNEL_SCALAR, 64, g});
     }
 
     // tuning steps the state: keep a copy and restore it afterwards; the

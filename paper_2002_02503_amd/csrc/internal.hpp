@@ -85,8 +85,9 @@ hipError_t launch_unswap(int lat, int dtype, const void* src, void* dst, const S
 int vec_sites_per_lane(int lat, int dtype);
 hipError_t launch_step_vec(int lat, int dtype, int K, int kind, const void* src, void* dst, const VecGeom& geo,
                            double omega, double theta, hipStream_t s);
+// staged: whole-row tiles written through LDS as one contiguous run.
 hipError_t launch_step_batch(int lat, int dtype, int K, int kind, const void* src, void* dst, const TileDesc* tiles,
-                             int ntiles, double theta, int block, int grid, hipStream_t s);
+                             int ntiles, double theta, int block, int grid, bool staged, hipStream_t s);
 // Readers of the stored state.  swapped: the state is in the swapped layout
 // the in-place step leaves after an odd number of steps (single box).
 hipError_t launch_moments(int lat, int dtype, const void* src, bool swapped, double* rho, double* u,

@@ -448,12 +448,12 @@ hipError_t launch_step_ip(int lat, int dtype, int K, int kind, void* buf, bool f
 }
 
 hipError_t launch_step_batch(int lat, int dtype, int K, int kind, const void* src, void* dst, const TileDesc* tiles,
-                             int ntiles, double theta, int block, int grid, hipStream_t s)
+                             int ntiles, double theta, int block, int grid, bool staged, hipStream_t s)
 {
     return by_pair(lat, dtype, [&](auto Lt, auto* Sp) {
         using L = decltype(Lt);
         using S = std::remove_pointer_t<decltype(Sp)>;
-        return launch_step_batch_l<L, S>(K, kind, src, dst, tiles, ntiles, theta, block, grid, s);
+        return launch_step_batch_l<L, S>(K, kind, src, dst, tiles, ntiles, theta, block, grid, staged, s);
     });
 }
 

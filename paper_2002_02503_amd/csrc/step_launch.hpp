@@ -34,10 +34,11 @@ template <class L, class S>
 hipError_t launch_step_vec_l(int K, int kind, const void* src, void* dst, const VecGeom& geo, double omega,
                              double theta, hipStream_t s);
 
-// Batch of boxes: a fixed grid walks the tile table.
+// Batch of boxes: a fixed grid walks the tile table; staged: whole-row tiles
+// are written through LDS as one contiguous run.
 template <class L, class S>
 hipError_t launch_step_batch_l(int K, int kind, const void* src, void* dst, const TileDesc* tiles, int ntiles,
-                               double theta, int block, int grid, hipStream_t s);
+                               double theta, int block, int grid, bool staged, hipStream_t s);
 
 #define LBM_DECLARE_STEP_INSTANCES(EXT, L, S)                                                                    \
     EXT template hipError_t launch_step_l<L, S>(int, int, const void*, void*, const StepGeom&, double, double,  \
@@ -50,7 +51,7 @@ hipError_t launch_step_batch_l(int K, int kind, const void* src, void* dst, cons
 
 #define LBM_DECLARE_BATCH_INSTANCES(EXT, L, S)                                                                 \
     EXT template hipError_t launch_step_batch_l<L, S>(int, int, const void*, void*, const TileDesc*, int,    \
-                                                      double, int, int, hipStream_t);
+                                                      double, int, int, bool, hipStream_t);
 
 #define LBM_EXTERN_PAIR(L, S)                  \
     LBM_DECLARE_STEP_INSTANCES(extern, L, S)   \
