@@ -69,7 +69,7 @@ def timed_steps(sim, steps: int, warmup: int) -> float:
     return e0.elapsed_time(e1) / steps
 
 
-KERNEL_NAMES = {1: "scalar", 2: "row_wave", 3: "in_place", 4: "two_row", 5: "staged"}
+KERNEL_NAMES = {1: "scalar", 2: "row_wave", 3: "in_place", 4: "two_row"}
 KERNEL_SYMBOLS = {"scalar": "k_step", "row_wave": "k_step_vec", "in_place": "k_step_ip", "two_row": "k_step_pair"}
 
 

@@ -67,7 +67,7 @@ typedef enum {
     LBM_COLLISION_BGK = 1        /* eq. BGK, f' = f - (f - f^eq)/tau, with the same truncated f^eq */
 } lbm_collision;
 
-/* Step-kernel variants (lbm_set_kernel): 1-4 for a single box, 5 for a batch. */
+/* Step-kernel variants for a single box (lbm_set_kernel). */
 typedef enum {
     LBM_KERNEL_AUTO = 0,      /* the scalar step unless a tuned choice was set */
     LBM_KERNEL_SCALAR = 1,    /* one site per thread, 4/8-byte accesses */
@@ -75,10 +75,8 @@ typedef enum {
     LBM_KERNEL_IN_PLACE = 3,  /* one site per thread on one buffer: each step reads and writes the same
                                  elements, alternating between two layouts of the state (bit-identical
                                  results, half the memory) */
-    LBM_KERNEL_TWO_ROW = 4,   /* two sites per thread (rows 2j and 2j+1, ny even): the second site's loads
+    LBM_KERNEL_TWO_ROW = 4    /* two sites per thread (rows 2j and 2j+1, ny even): the second site's loads
                                  are in flight while the first collides (bit-identical results) */
-    LBM_KERNEL_STAGED = 5     /* batches only: a tile of whole rows (rows * nx <= 64) collects its outputs in
-                                 LDS and writes them as one contiguous run (bit-identical results) */
 } lbm_kernel;
 
 typedef struct {
@@ -136,13 +134,19 @@ lbm_status lbm_set_collision(lbm_t h, int32_t collision, double theta);
  * The caller keeps ownership of the stream; it must outlive the handle's use. */
 lbm_status lbm_set_stream(lbm_t h, void* hip_stream);
 
-/* Bytes needed for one population buffer: Q * nsites stored values, rounded
- * up to a multiple of 256.  Layout (row-tiled structure of arrays): box b
- * holds elements [Q O_b, Q (O_b + n_b)), O_b its first global site; inside it
- * x-row r = z * ny + y is a tile of Q * nx values with population i of site x
- * at r * Q * nx + m(i) * nx + x, where the tile row m(i) is the rank of c_i in
- * the order of increasing (c_z, c_y, c_x) and i the order of
- * lbm_lattice_table. */
+/* Bytes needed for one population buffer: Q * nstored stored values, rounded
+ * up to a multiple of 256.  Layout (blocked structure of arrays): the local
+ * sites l = (z * ny + y) * nx + x of a box are cut into blocks of w
+ * consecutive sites, and block l / w holds Q runs of w values, population i of
+ * site l at element l / w * Q * w + m(i) * w + l % w from the box's first
+ * element, where the tile row m(i) is the rank of c_i in the order of
+ * increasing (c_z, c_y, c_x) and i the order of lbm_lattice_table.
+ *   - A single box: w = nx (each x-row is one block, "row tiles"), and
+ *     nstored = nx * ny * nz.
+ *   - A batch: w = 64, and each box is padded to a whole number of blocks
+ *     (n_b rounded up to a multiple of 64); box b starts at element Q P_b,
+ *     P_b the padded site count of the boxes before it.  The padding is zero
+ *     after lbm_init and lbm_set_state and never read or written by a step. */
 lbm_status lbm_state_bytes(lbm_t h, size_t* bytes_each);
 
 /* Use caller-owned device memory (e.g. two torch tensors) for the two
@@ -173,8 +177,7 @@ lbm_status lbm_set_graph_chunk(lbm_t h, int32_t steps);
 /* Launch shape: threads per block (64, 128 or 256; 0 = default) and,
  * for batches, the number of blocks of the persistent step kernel (0 = enough
  * blocks for every tile to get its own wave; a batch tile is one wave's work:
- * whole x-rows of one plane with rows * nx <= 64, or 64 sites of a longer
- * row).  Only before lbm_init. */
+ * one 64-site block of a box's layout).  Only before lbm_init. */
 lbm_status lbm_set_launch(lbm_t h, int32_t block, int32_t grid);
 
 /* Choose the single-box step kernel.  All variants compute the same bits.
@@ -187,11 +190,9 @@ lbm_status lbm_set_launch(lbm_t h, int32_t block, int32_t grid);
  * layout (population i of site x at site x + c_i, tile row m(opp(i))); the
  * moments, totals and residual read it as it is, and lbm_get_state returns the
  * natural layout (rearranged on the host).  Switching kernels later (lbm_tune)
- * allocates the second buffer.  Batches always use the tiled batched kernel,
- * with direct stores (LBM_KERNEL_AUTO, LBM_KERNEL_SCALAR) or staged ones
- * (LBM_KERNEL_STAGED: rows whose population rows do not fill whole 128-byte
- * lines are otherwise written as partial lines); the other variants are
- * LBM_EINVAL for a batch, and LBM_KERNEL_STAGED for a single box.
+ * allocates the second buffer.  Batches always use the batched kernel (one
+ * wave per 64-site block); for them LBM_KERNEL_AUTO and LBM_KERNEL_SCALAR are
+ * accepted and the other variants are LBM_EINVAL.
  * LBM_KERNEL_TWO_ROW needs a single box with ny even (else LBM_EINVAL).
  * May be called at any time: on an initialised handle the state is first
  * brought to the natural layout (which may allocate the second buffer), and
@@ -202,9 +203,8 @@ lbm_status lbm_set_kernel(lbm_t h, int32_t kernel);
  * events, in three interleaved rounds, and keep the candidate with the fastest
  * round.  Single box: the scalar step at 64/128/256 threads per block, the
  * in-place step and the two-row step (ny even) at 256, and the row-wave step
- * where it applies.  Batch: the direct-store and staged kernels at 64/128/256
- * threads with one wave per tile, and the direct-store kernel with
- * 1024/2048/4096 persistent blocks of 64 threads.  The state is saved before and restored
+ * where it applies.  Batch: 64/128/256 threads per block, with one wave per
+ * 64-site block of the layout or 1024/2048/4096 persistent blocks.  The state is saved before and restored
  * after, so t and the populations are unchanged (all candidates compute the
  * same bits).  Choices are appended to the text file `cache_path` (NULL: the
  * path in the environment variable LBM_TUNE_CACHE, or no cache); a later call
@@ -231,7 +231,7 @@ lbm_status lbm_residual(lbm_t h, const double* rho_ref, const double* u_ref, int
                         double out[4]);
 
 /* Checkpoint: bytes needed by lbm_get_state (a header plus the raw stored
- * populations). */
+ * populations, Q * nstored values, padding included). */
 lbm_status lbm_checkpoint_bytes(lbm_t h, size_t* bytes);
 
 /* Copy the state to host memory `buf` of at least lbm_checkpoint_bytes(): a

@@ -6,6 +6,7 @@
 // checkpoint format and error reporting.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -52,6 +53,7 @@ lbm_status fail_hip(hipError_t e, const char* what)
     } while (0)
 
 constexpr int kChunkSites = 4096;   // sites per reduction chunk
+constexpr int kBlockSites = 64;     // sites per block of a batched box's layout (one wave)
 constexpr int kDefaultGraphChunk = 32;
 constexpr int kTuneRounds = 3;
 constexpr uint64_t kCkptMagic = 0x314b4350434d424cULL;  // "LBMCPCK1"
@@ -76,8 +78,11 @@ struct lbm_ctx {
     int nbox = 0;
     std::vector<int64_t> dims;      // nbox * 3
     std::vector<double> tau;        // nbox
-    std::vector<int64_t> offset;    // nbox
+    std::vector<int64_t> offset;    // nbox: first global site (field index)
+    std::vector<int64_t> mem;       // nbox: element offset of the populations
     int64_t nsites = 0;
+    int64_t nstored = 0;            // stored sites, with the blocked layout's padding
+    bool aligned_rows = false;      // batch: every box has nx % 64 == 0
     size_t elem = 0;                // bytes per stored population
     size_t state_bytes = 0;
     void* buf[2] = {nullptr, nullptr};
@@ -132,7 +137,7 @@ int step_kind(const lbm_ctx* h)
 
 int effective_kernel(const lbm_ctx* h)
 {
-    if (!is_single(h)) return h->kernel == LBM_KERNEL_STAGED ? LBM_KERNEL_STAGED : LBM_KERNEL_SCALAR;
+    if (!is_single(h)) return LBM_KERNEL_SCALAR;
     if (h->kernel == LBM_KERNEL_AUTO) return LBM_KERNEL_SCALAR;  // measured faster unless tuned otherwise
     return h->kernel;
 }
@@ -215,44 +220,30 @@ lbm_status device_check(int* dev)
     return LBM_OK;
 }
 
-// Wave tiles of the batched step (step_batch.hpp): whole x-rows of one plane
-// with rows * nx <= 64, or 64-site pieces of a row when nx > 64.  The table
-// does not depend on the block size.
+// Wave tiles of the batched step (step_batch.hpp): one per 64-site block of
+// each box.  The table does not depend on the block size.
 lbm_status build_tiles(lbm_ctx* h)
 {
-    constexpr int kWave = 64;
     if (is_single(h)) return LBM_OK;
     if (h->d_tiles) return LBM_OK;
     std::vector<TileDesc> tiles;
     for (int b = 0; b < h->nbox; ++b) {
-        const int nx = int(h->dims[3 * b]), ny = int(h->dims[3 * b + 1]), nz = int(h->dims[3 * b + 2]);
+        const int64_t nx = h->dims[3 * b], ny = h->dims[3 * b + 1], nz = h->dims[3 * b + 2];
+        const int64_t n = nx * ny * nz;
         TileDesc t{};
-        t.nx = nx;
-        t.ny = ny;
-        t.nz = nz;
-        t.inv_nx = float(1.0 / double(nx));
-        t.offset = h->offset[b];
+        t.nx = int(nx);
+        t.ny = int(ny);
+        t.nz = int(nz);
+        t.mem = h->mem[b];
         t.omega = 1.0 - 1.0 / h->tau[b];
         t.box = b;
-        for (int z = 0; z < nz; ++z) {
-            t.z = z;
-            if (nx <= kWave) {
-                const int per = kWave / nx;  // whole rows per tile
-                for (int y = 0; y < ny; y += per) {
-                    t.y0 = y;
-                    t.rows = (ny - y < per) ? ny - y : per;
-                    t.x0 = 0;
-                    tiles.push_back(t);
-                }
-            } else {
-                for (int y = 0; y < ny; ++y)
-                    for (int x0 = 0; x0 < nx; x0 += kWave) {
-                        t.y0 = y;
-                        t.rows = 1;
-                        t.x0 = x0;
-                        tiles.push_back(t);
-                    }
-            }
+        for (int64_t l0 = 0; l0 < n; l0 += kBlockSites) {
+            t.x0 = int(l0 % nx);
+            t.y0 = int((l0 / nx) % ny);
+            t.z0 = int(l0 / (nx * ny));
+            t.blk = int(l0 / kBlockSites);
+            t.count = int(std::min<int64_t>(kBlockSites, n - l0));
+            tiles.push_back(t);
         }
     }
     HIP_TRY(hipMalloc(&h->d_tiles, tiles.size() * sizeof(TileDesc)), "hipMalloc(tiles)");
@@ -293,20 +284,31 @@ lbm_status create_common(lbm_t* out, int32_t lattice, int32_t nbox, const int64_
     h->dims.assign(dims, dims + 3 * nbox);
     h->tau.assign(tau, tau + nbox);
     h->offset.resize(nbox);
+    h->mem.resize(nbox);
     h->device = dev;
-    int64_t off = 0;
+    // A single box is stored in row tiles (blocks of w = nx sites); the boxes
+    // of a batch in blocks of 64 sites, each box padded to whole blocks.
+    int64_t off = 0, stored = 0;
+    bool aligned = true;
     for (int b = 0; b < nbox; ++b) {
+        const int64_t n = dims[3 * b] * dims[3 * b + 1] * dims[3 * b + 2];
         h->offset[b] = off;
-        off += dims[3 * b] * dims[3 * b + 1] * dims[3 * b + 2];
+        h->mem[b] = stored * L.Q;
+        off += n;
+        stored += (nbox == 1) ? n : (n + kBlockSites - 1) / kBlockSites * kBlockSites;
+        aligned = aligned && dims[3 * b] % kBlockSites == 0;
     }
     h->nsites = off;
+    h->nstored = stored;
+    h->aligned_rows = aligned;
     h->elem = storage_bytes(dtype);
-    // row-tiled layout: Q * nsites elements, allocation rounded to 256 bytes
-    h->state_bytes = ((size_t(h->nsites) * size_t(L.Q) * h->elem + 255) / 256) * 256;
+    // Q * nstored elements, allocation rounded to 256 bytes
+    h->state_bytes = ((size_t(h->nstored) * size_t(L.Q) * h->elem + 255) / 256) * 256;
     if (nbox > 1)
         for (int b = 0; b < nbox; ++b) {
             const uint64_t nb = uint64_t(dims[3 * b]) * uint64_t(dims[3 * b + 1]) * uint64_t(dims[3 * b + 2]);
-            if (nb * uint64_t(L.Q) * h->elem >= (uint64_t(1) << 31)) {
+            const uint64_t padded = (nb + kBlockSites - 1) / kBlockSites * kBlockSites;
+            if (padded * uint64_t(L.Q) * h->elem >= (uint64_t(1) << 31)) {
                 delete h;
                 return fail(LBM_EINVAL, "box %d of a batch must hold less than 2 GiB of populations", b);
             }
@@ -355,7 +357,9 @@ lbm_status create_common(lbm_t* out, int32_t lattice, int32_t nbox, const int64_
             boxes[b].nx = int(dims[3 * b]);
             boxes[b].ny = int(dims[3 * b + 1]);
             boxes[b].nz = int(dims[3 * b + 2]);
+            boxes[b].w = (nbox == 1) ? boxes[b].nx : kBlockSites;
             boxes[b].offset = h->offset[b];
+            boxes[b].mem = h->mem[b];
             boxes[b].omega = 1.0 - 1.0 / tau[b];
         }
         if ((e = hipMalloc(&h->d_boxes, boxes.size() * sizeof(BoxDesc))) != hipSuccess)
@@ -398,6 +402,18 @@ lbm_status ensure_second(lbm_ctx* h)
 
 bool in_place(const lbm_ctx* h) { return is_single(h) && effective_kernel(h) == LBM_KERNEL_IN_PLACE; }
 
+// The padding sites of a batch's blocked layout are never read or written by
+// the step; zero them in both buffers (before lbm_init or lbm_set_state writes
+// the state), so that checkpoints are deterministic.  Not part of any
+// captured graph.
+lbm_status clear_padding(lbm_ctx* h)
+{
+    if (h->nstored == h->nsites) return LBM_OK;
+    for (int k = 0; k < 2; ++k)
+        if (h->buf[k]) HIP_TRY(hipMemsetAsync(h->buf[k], 0, h->state_bytes, h->stream), "clear the state buffers");
+    return LBM_OK;
+}
+
 StepGeom single_geom(const lbm_ctx* h, int block)
 {
     StepGeom geo;
@@ -436,7 +452,7 @@ hipError_t launch_one(lbm_ctx* h, int parity, hipStream_t s)
         return launch_step(h->lattice, h->dtype, h->K, step_kind(h), src, dst, single_geom(h, block),
                            1.0 - 1.0 / h->tau[0], h->theta, block, effective_kernel(h) == LBM_KERNEL_TWO_ROW, s);
     return launch_step_batch(h->lattice, h->dtype, h->K, step_kind(h), src, dst, h->d_tiles, h->ntiles, h->theta,
-                             block, h->grid, h->kernel == LBM_KERNEL_STAGED, s);
+                             block, h->grid, h->aligned_rows, s);
 }
 
 // Where the current state is, and whether the in-place step left it in the
@@ -641,10 +657,8 @@ lbm_status lbm_set_kernel(lbm_t h, int32_t kernel)
 {
     if (lbm_status st = check_handle(h)) return st;
     if (kernel != LBM_KERNEL_AUTO && kernel != LBM_KERNEL_SCALAR && kernel != LBM_KERNEL_ROW_WAVE &&
-        kernel != LBM_KERNEL_IN_PLACE && kernel != LBM_KERNEL_TWO_ROW && kernel != LBM_KERNEL_STAGED)
+        kernel != LBM_KERNEL_IN_PLACE && kernel != LBM_KERNEL_TWO_ROW)
         return fail(LBM_EINVAL, "unknown kernel variant %d", kernel);
-    if (kernel == LBM_KERNEL_STAGED && is_single(h))
-        return fail(LBM_EINVAL, "the staged step is the batched step's; a single box writes whole rows already");
     if (kernel == LBM_KERNEL_IN_PLACE && !is_single(h))
         return fail(LBM_EINVAL, "the in-place step is for a single box; batches use the tiled batched kernel");
     if (kernel == LBM_KERNEL_TWO_ROW && (!is_single(h) || h->dims[1] % 2 != 0))
@@ -667,6 +681,7 @@ lbm_status lbm_init(lbm_t h, const double* rho, const double* u, int32_t on_devi
     HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
     if (lbm_status st = ensure_buffers(h)) return st;
     if (lbm_status st = build_tiles(h)) return st;
+    if (lbm_status st = clear_padding(h)) return st;
     const size_t n = size_t(h->nsites);
     double *drho = nullptr, *du = nullptr;
     bool t1 = false, t2 = false;
@@ -800,7 +815,6 @@ lbm_status lbm_tune(lbm_t h, int32_t steps, const char* cache_path)
     if (cache_lookup(cache_path, key, &best)) {
         if (best.kernel == LBM_KERNEL_ROW_WAVE && !row_wave_sites(h)) best.kernel = LBM_KERNEL_SCALAR;
         if (best.kernel == LBM_KERNEL_IN_PLACE && !is_single(h)) best.kernel = LBM_KERNEL_SCALAR;
-        if (best.kernel == LBM_KERNEL_STAGED && is_single(h)) best.kernel = LBM_KERNEL_SCALAR;
         if (best.kernel == LBM_KERNEL_TWO_ROW && (!is_single(h) || h->dims[1] % 2 != 0))
             best.kernel = LBM_KERNEL_SCALAR;
         return apply_choice(h, best);
@@ -814,9 +828,8 @@ lbm_status lbm_tune(lbm_t h, int32_t steps, const char* cache_path)
         if (h->dims[1] % 2 == 0) cand.push_back({LBM_KERNEL_TWO_ROW, 256, 0});
         if (row_wave_sites(h)) cand.push_back({LBM_KERNEL_ROW_WAVE, 0, 0});
     } else {
-        for (int k : {LBM_KERNEL_SCALAR, LBM_KERNEL_STAGED})
-            for (int b : {64, 128, 256}) cand.push_back({k, b, 0});
-        for (int g : {1024, 2048, 4096}) cand.push_back({LBM_KERNEL_SCALAR, 64, g});
+        for (int b : {64, 128, 256})
+            for (int g : {0, 1024, 2048, 4096}) cand.push_back({LBM_KERNEL_SCALAR, b, g});
     }
 
     // tuning steps the state: keep a copy and restore it afterwards; the
@@ -962,7 +975,7 @@ lbm_status lbm_checkpoint_bytes(lbm_t h, size_t* bytes)
 {
     if (lbm_status st = check_handle(h)) return st;
     if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
-    *bytes = sizeof(CkptHeader) + size_t(h->lat.Q) * size_t(h->nsites) * h->elem;
+    *bytes = sizeof(CkptHeader) + size_t(h->lat.Q) * size_t(h->nstored) * h->elem;
     return LBM_OK;
 }
 
@@ -990,7 +1003,7 @@ lbm_status lbm_get_state(lbm_t h, void* buf, size_t bytes)
     const void* state = nullptr;
     bool swapped = false;
     state_view(h, &state, &swapped);
-    const size_t payload = size_t(h->lat.Q) * size_t(h->nsites) * h->elem;
+    const size_t payload = size_t(h->lat.Q) * size_t(h->nstored) * h->elem;
     if (!swapped) {
         HIP_TRY(hipMemcpyAsync(dst, state, payload, hipMemcpyDeviceToHost, h->stream), "copy state to host");
         HIP_TRY(hipStreamSynchronize(h->stream), "get_state synchronize");
@@ -1026,7 +1039,8 @@ lbm_status lbm_set_state(lbm_t h, const void* buf, size_t bytes)
     if (lbm_status st = ensure_buffers(h)) return st;
     if (lbm_status st = build_tiles(h)) return st;
     const char* src = static_cast<const char*>(buf) + sizeof(hd);
-    HIP_TRY(hipMemcpyAsync(h->buf[0], src, size_t(h->lat.Q) * size_t(h->nsites) * h->elem, hipMemcpyHostToDevice,
+    if (lbm_status st = clear_padding(h)) return st;
+    HIP_TRY(hipMemcpyAsync(h->buf[0], src, size_t(h->lat.Q) * size_t(h->nstored) * h->elem, hipMemcpyHostToDevice,
                            h->stream),
             "copy state to device");
     HIP_TRY(hipStreamSynchronize(h->stream), "set_state synchronize");

@@ -1,15 +1,15 @@
 // Library-internal declarations shared by the C-ABI implementation and the
 // kernel launchers.
 //
-// Population layout ("row-tiled structure of arrays").  Box b starts at site
-// offset O_b of the concatenated site space and holds nx * ny * nz sites.
-// Its populations occupy elements [Q O_b, Q (O_b + n_b)) of a buffer; inside
-// the box, x-row r = z * ny + y is one tile of Q * nx elements in which
-// population i of site x sits at r Q nx + m(i) nx + x, with the tile rows
-// m ordered by (c_z, c_y, c_x) (lattice.hpp, mem_row).  A row tile is thus a
-// small structure of arrays: every population row is contiguous in x, a step
-// writes each tile as one contiguous run of Q * nx elements, and the
-// populations it pulls from one neighbouring tile are adjacent rows.
+// Population layout ("blocked structure of arrays", BoxDesc).  The local
+// sites of a box, x fastest, are cut into blocks of w consecutive sites; a
+// block holds Q runs of w values, population i in run m(i), with the runs
+// ordered by (c_z, c_y, c_x) (lattice.hpp, mem_row).  A single box has w = nx:
+// each x-row is one block ("row tile"), every population row is contiguous in
+// x, a step writes each tile as one contiguous run of Q * nx elements, and
+// the populations it pulls from one neighbouring tile are adjacent rows.  The
+// boxes of a batch have w = 64, one wavefront's sites, whatever their row
+// length.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -36,23 +36,32 @@ struct VecGeom {
     int nrows;            // ny * nz
 };
 
-// A tile of the batched step, one wavefront's work: in box `box`, plane z,
-// the x-rows y0 .. y0 + rows - 1 (rows * nx <= 64), or, when nx exceeds 64,
-// the 64 sites of row y0 from x0 on.  The tile carries its box's geometry, first
-// site and relaxation factor, so a block starts after one 64-byte scalar load.
+// A tile of the batched step, one wavefront's work: block `blk` of box `box`,
+// that is its local sites blk * 64 .. blk * 64 + count - 1 (x fastest, then
+// y, then z), the first of which is (x0, y0, z0).  The tile carries its box's
+// geometry, population offset and relaxation factor, so a wave starts after
+// one 64-byte scalar load.
 struct alignas(64) TileDesc {
-    int z, y0, rows, x0;
     int nx, ny, nz;
-    float inv_nx;         // 1 / nx, for the lane -> (row, x) split of a tile
-    long long offset;     // the box's first global site
+    int x0, y0, z0;
+    int blk, count;
+    long long mem;        // element offset of the box's populations
     double omega;         // 1 - 1/tau of the box
     int box;
 };
 static_assert(sizeof(TileDesc) == 64, "tile descriptor is one scalar load");
 
+// Population layout of a box: its local sites l = (z * ny + y) * nx + x are
+// cut into blocks of w consecutive sites, and block l / w holds Q runs of w
+// values, population i of site l at element
+//   mem + (l / w) * Q * w + m(i) * w + l % w      (m: tile row, lattice.hpp).
+// A single box has w = nx (a block is an x-row: the row-tiled layout); the
+// boxes of a batch have w = 64, each padded to a whole number of blocks.
 struct BoxDesc {
     int nx, ny, nz;
-    long long offset;     // O_b: global index of the box's first site
+    int w;                // sites per block
+    long long offset;     // O_b: global index of the box's first site (fields)
+    long long mem;        // element offset of the box's populations
     double omega;         // 1 - 1/tau
 };
 
@@ -85,9 +94,10 @@ hipError_t launch_unswap(int lat, int dtype, const void* src, void* dst, const S
 int vec_sites_per_lane(int lat, int dtype);
 hipError_t launch_step_vec(int lat, int dtype, int K, int kind, const void* src, void* dst, const VecGeom& geo,
                            double omega, double theta, hipStream_t s);
-// staged: whole-row tiles written through LDS as one contiguous run.
+// Batch of boxes in the blocked layout.  aligned_rows: every box has nx a
+// multiple of 64, so populations with c_x = 0 are read in whole blocks.
 hipError_t launch_step_batch(int lat, int dtype, int K, int kind, const void* src, void* dst, const TileDesc* tiles,
-                             int ntiles, double theta, int block, int grid, bool staged, hipStream_t s);
+                             int ntiles, double theta, int block, int grid, bool aligned_rows, hipStream_t s);
 // Readers of the stored state.  swapped: the state is in the swapped layout
 // the in-place step leaves after an odd number of steps (single box).
 hipError_t launch_moments(int lat, int dtype, const void* src, bool swapped, double* rho, double* u,

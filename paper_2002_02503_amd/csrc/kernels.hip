@@ -22,12 +22,13 @@ namespace lbm {
 // ---------------------------------------------------------------------------
 
 // Element index of population 0 of a site, relative to the box's first
-// element: row tile r = local / nx, x = local % nx.
-__device__ __forceinline__ long long site_elem(long long local, int nx, int Q)
+// element, in a layout of w-site blocks (BoxDesc): block local / w, position
+// local % w; population i is m(i) * w further on.
+__device__ __forceinline__ long long site_elem(long long local, int w, int Q)
 {
-    const long long r = local / nx;
-    const long long x = local - r * nx;
-    return r * Q * nx + x;
+    const long long r = local / w;
+    const long long x = local - r * w;
+    return r * Q * w + x;
 }
 
 // Initialisation: f := f^eq_K(rho, u) (eq. hermite), evaluated in double and
@@ -40,10 +41,10 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ rho, co
     using ST = Store<S>;
     const ChunkDesc ch = chunks[blockIdx.x];
     const BoxDesc b = boxes[ch.box];
-    S* base = dst + (long long)L::Q * b.offset;
+    S* base = dst + b.mem;
     for (int k = threadIdx.x; k < ch.count; k += blockDim.x) {
         const long long s = ch.start + k;
-        const long long e = site_elem(s - b.offset, b.nx, L::Q);
+        const long long e = site_elem(s - b.offset, b.w, L::Q);
         const double ux = u[s];
         const double uy = u[nsites + s];
         const double uz = (L::D == 3) ? u[2 * nsites + s] : 0.0;
@@ -52,15 +53,16 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ rho, co
         unroll<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             constexpr int m = mem_row<L>(i);
-            ST::put_d(base + e + (long long)m * b.nx, g[i]);
+            ST::put_d(base + e + (long long)m * b.w, g[i]);
         });
     }
 }
 
 // rho - 1 and rho u (eq. mme) of one stored site, in double (outside the
-// step, for output and reductions).  `p` points at population 0 of the site.
+// step, for output and reductions).  `p` points at population 0 of the site,
+// w is the block width of the box's layout.
 template <class L, class S>
-__device__ __forceinline__ void site_moments(const S* __restrict__ p, int nx, double& dsum, double (&j)[3])
+__device__ __forceinline__ void site_moments(const S* __restrict__ p, int w, double& dsum, double (&j)[3])
 {
     using ST = Store<S>;
     dsum = 0.0;
@@ -69,7 +71,7 @@ __device__ __forceinline__ void site_moments(const S* __restrict__ p, int nx, do
         constexpr int i = decltype(I)::value;
         constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
         constexpr int m = mem_row<L>(i);
-        const double gi = double(ST::get(p + (long long)m * nx));
+        const double gi = double(ST::get(p + (long long)m * w));
         dsum += gi;
         if constexpr (cx != 0) j[0] += double(cx) * gi;
         if constexpr (cy != 0) j[1] += double(cy) * gi;
@@ -84,7 +86,8 @@ __device__ __forceinline__ void site_moments(const S* __restrict__ p, int nx, do
 
 // The same for a box whose state the in-place step left in the swapped layout:
 // population i of site (x, y, z) sits at site (x, y, z) + c_i, tile row
-// m(opp(i)).  `local` is the site's index inside its box.
+// m(opp(i)).  `local` is the site's index inside its box.  Single boxes only
+// (row tiles, w = nx).
 template <class L, class S>
 __device__ __forceinline__ void swapped_site_moments(const S* __restrict__ base, long long local, const BoxDesc& b,
                                                      double& dsum, double (&j)[3])
@@ -119,7 +122,7 @@ __device__ __forceinline__ void stored_site_moments(const S* __restrict__ base, 
                                                     double& dsum, double (&j)[3])
 {
     if constexpr (SWAPPED) swapped_site_moments<L, S>(base, local, b, dsum, j);
-    else site_moments<L, S>(base + site_elem(local, b.nx, L::Q), b.nx, dsum, j);
+    else site_moments<L, S>(base + site_elem(local, b.w, L::Q), b.w, dsum, j);
 }
 
 template <class L, class S, bool SWAPPED>
@@ -129,7 +132,7 @@ __global__ __launch_bounds__(256) void k_moments(const S* __restrict__ src, doub
 {
     const ChunkDesc ch = chunks[blockIdx.x];
     const BoxDesc b = boxes[ch.box];
-    const S* base = src + (long long)L::Q * b.offset;
+    const S* base = src + b.mem;
     for (int k = threadIdx.x; k < ch.count; k += blockDim.x) {
         const long long s = ch.start + k;
         double d, j[3];
@@ -176,7 +179,7 @@ __global__ __launch_bounds__(kRedBlock) void k_totals_partial(const S* __restric
 {
     const ChunkDesc ch = chunks[blockIdx.x];
     const BoxDesc b = boxes[ch.box];
-    const S* base = src + (long long)L::Q * b.offset;
+    const S* base = src + b.mem;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int k = threadIdx.x; k < ch.count; k += kRedBlock) {
         double d, j[3];
@@ -223,7 +226,7 @@ __global__ __launch_bounds__(kRedBlock) void k_residual_partial(const S* __restr
 {
     const ChunkDesc ch = chunks[blockIdx.x];
     const BoxDesc b = boxes[ch.box];
-    const S* base = src + (long long)L::Q * b.offset;
+    const S* base = src + b.mem;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};  // max |du|, sum du^2, max |drho|, sum drho^2
     for (int k = threadIdx.x; k < ch.count; k += kRedBlock) {
         const long long s = ch.start + k;
@@ -448,12 +451,12 @@ hipError_t launch_step_ip(int lat, int dtype, int K, int kind, void* buf, bool f
 }
 
 hipError_t launch_step_batch(int lat, int dtype, int K, int kind, const void* src, void* dst, const TileDesc* tiles,
-                             int ntiles, double theta, int block, int grid, bool staged, hipStream_t s)
+                             int ntiles, double theta, int block, int grid, bool aligned_rows, hipStream_t s)
 {
     return by_pair(lat, dtype, [&](auto Lt, auto* Sp) {
         using L = decltype(Lt);
         using S = std::remove_pointer_t<decltype(Sp)>;
-        return launch_step_batch_l<L, S>(K, kind, src, dst, tiles, ntiles, theta, block, grid, staged, s);
+        return launch_step_batch_l<L, S>(K, kind, src, dst, tiles, ntiles, theta, block, grid, aligned_rows, s);
     });
 }
 

@@ -34,11 +34,11 @@ template <class L, class S>
 hipError_t launch_step_vec_l(int K, int kind, const void* src, void* dst, const VecGeom& geo, double omega,
                              double theta, hipStream_t s);
 
-// Batch of boxes: a fixed grid walks the tile table; staged: whole-row tiles
-// are written through LDS as one contiguous run.
+// Batch of boxes in the blocked layout: one wave per tile; a fixed grid
+// walks the tile table.
 template <class L, class S>
 hipError_t launch_step_batch_l(int K, int kind, const void* src, void* dst, const TileDesc* tiles, int ntiles,
-                               double theta, int block, int grid, bool staged, hipStream_t s);
+                               double theta, int block, int grid, bool aligned_rows, hipStream_t s);
 
 #define LBM_DECLARE_STEP_INSTANCES(EXT, L, S)                                                                    \
     EXT template hipError_t launch_step_l<L, S>(int, int, const void*, void*, const StepGeom&, double, double,  \
