@@ -26,8 +26,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS & % HBM roofline, D3Q19 256³ FP32 vs FP16-storage at stated error"
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E peak
-def traffic_file(kernel: str) -> str:
-    """Committed counter summary of the headline step for one kernel variant."""
+def traffic_file(kernel: str, workload: str = "turbulence256") -> str:
+    """Committed counter summary of the step for one kernel variant, on the
+    headline box or on the 256-box batch."""
+    if workload == "batch256":
+        return os.path.join(ROOT, "profiles", "traffic_batch256_fp32.json")
     return os.path.join(ROOT, "profiles", f"traffic_d3q19_256_fp32_{kernel}.json")
 # what decides the step kernel's machine code: its sources and the compiler flags
 def _kernel_sources() -> list:
@@ -94,13 +97,13 @@ def measure_box(lattice, dims, tau, dtype, rho, u, steps, warmup, tune=True, **k
             "block": info["block"], "grid": info["grid"]}
 
 
-def traffic_per_launch(kernel: str):
+def traffic_per_launch(kernel: str, workload: str = "turbulence256"):
     """HBM bytes per launch of the FP32 256^3 step of a kernel variant from the
     committed rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, scaled by the
     copy-kernel calibration), or None when absent or taken on other kernel
     sources.  For the in-place variant a launch is one of its two alternating
     forms, averaged over both."""
-    path = traffic_file(kernel)
+    path = traffic_file(kernel, workload)
     if not os.path.exists(path):
         return None, "no counter summary"
     with open(path) as f:
@@ -179,6 +182,9 @@ def main():
     ap.add_argument("--kernel", choices=["tune", "scalar", "row_wave", "in_place", "two_row"], default="tune",
                     help="headline step kernel: autotuned (default) or pinned")
     ap.add_argument("--block", type=int, default=256, help="threads per block when --kernel is pinned")
+    ap.add_argument("--workload", choices=["turbulence256", "batch256"], default="turbulence256",
+                    help="turbulence256: the headline box (default); batch256: only the 256-box FP32 batch, "
+                         "with its own roofline (a profiling aid)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -192,6 +198,9 @@ def main():
 
     torch.cuda.set_device(0)
     lbm.load_library()
+    if args.workload == "batch256":
+        batch_only(args)
+        return
     tau = 0.51
     log("generating the 256^3 turbulence field")
     rho, u = inputs.turbulence(256)
@@ -222,14 +231,10 @@ def main():
             log(f"{dt} storage 256^3")
             variants[dt] = measure_box("D3Q19", (256, 256, 256), tau, dt, rho, u, args.steps, args.warmup)
         log("batched: 256 D3Q19 boxes, 1000 steps")
-        boxes = inputs.batch_boxes()
-        fields = [inputs.taylor_green_box(b["dims"], b["U"], 1.0 / 3.0) for b in boxes]
-        brho = np.concatenate([f[0].ravel() for f in fields])
-        bu = np.concatenate([f[1].reshape(3, -1) for f in fields], axis=1)
-        variants["batched_fp32"] = measure_box("D3Q19", [b["dims"] for b in boxes], [b["tau"] for b in boxes],
-                                               "fp32", brho, bu, 1000, args.warmup)
+        bdims, btaus, brho, bu = batch_fields()
+        variants["batched_fp32"] = measure_box("D3Q19", bdims, btaus, "fp32", brho, bu, 1000, args.warmup)
         variants["batched_fp32"]["config"] = "256 boxes, sides 16..64, tau 0.52..1, |U| <= 0.1, Taylor-Green"
-        del brho, bu, fields
+        del brho, bu
         log("D3Q39 192^3 FP32, 1000 steps")
         srho, su = inputs.shear_wave((192, 192, 192), 0.01, (0.2, 0.0, 0.0))
         variants["d3q39_fp32_192"] = measure_box("D3Q39", (192, 192, 192), 0.6, "fp32", srho, su, 1000,
@@ -277,6 +282,53 @@ def main():
         "variants": variants,
         "errors": errors,
     }
+    print(json.dumps(line), flush=True)
+
+
+def batch_fields():
+    """The 256-box workload: box parameters and Taylor-Green fields."""
+    import numpy as np
+
+    from paper_2002_02503_amd import inputs
+
+    boxes = inputs.batch_boxes()
+    fields = [inputs.taylor_green_box(b["dims"], b["U"], 1.0 / 3.0) for b in boxes]
+    rho = np.concatenate([f[0].ravel() for f in fields])
+    u = np.concatenate([f[1].reshape(3, -1) for f in fields], axis=1)
+    return [b["dims"] for b in boxes], [b["tau"] for b in boxes], rho, u
+
+
+def batch_only(args):
+    """--workload batch256: time the batched step alone and print one JSON line
+    with its roofline (the batched kernel is then the dominant one)."""
+    from paper_2002_02503_amd import lbm
+
+    dims, taus, rho, u = batch_fields()
+    log(f"batched FP32, 256 boxes: {args.warmup} warm-up + {args.steps} timed steps")
+    if args.kernel == "tune":
+        m = measure_box("D3Q19", dims, taus, "fp32", rho, u, args.steps, args.warmup)
+    elif args.kernel == "scalar":
+        m = measure_box("D3Q19", dims, taus, "fp32", rho, u, args.steps, args.warmup, tune=False, block=args.block)
+    else:
+        raise SystemExit("a batch runs the batched kernel: --kernel tune or scalar (block pinned)")
+    nsites = m["nsites"]
+    traffic, traffic_src = traffic_per_launch(m["kernel"], "batch256")
+    roofline = {"bound": "hbm", "achieved": m["achieved_GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": m["achieved_GBs"] / PEAK_HBM_GBS, "traffic": traffic,
+                "algorithmic_bytes_per_launch": m["bytes_per_site_update"] * nsites,
+                "kernel": "k_step_batch<D3Q19, float, K=3>", "launch": {"kernel": m["kernel"], "block": m["block"]},
+                "traffic_source": traffic_src}
+    copy_bytes = m["bytes_per_site_update"] // 2 * nsites
+    copy_ms = lbm.copy_probe(copy_bytes, reps=10)
+    copy_gbs = 2 * copy_bytes / (copy_ms * 1e-3) / 1e9
+    line = {"metric": "MLUPS & % HBM roofline, 256-box D3Q19 batch FP32", "value": m["value"], "unit": "MLUPS",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": m["ms_per_step"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "256 D3Q19 boxes, sides 16..64, tau 0.52..1, |U| <= 0.1, Taylor-Green, "
+                                   "FP32 storage, Hermite order 3, one launch per step", "nsites": nsites},
+            "roofline": roofline, "cpu_baseline": None,
+            "copy_probe": {"bytes_moved": 2 * copy_bytes, "GB_s": copy_gbs, "frac_of_peak": copy_gbs / PEAK_HBM_GBS},
+            "frac_of_copy": m["achieved_GBs"] / copy_gbs}
     print(json.dumps(line), flush=True)
 
 
