@@ -99,10 +99,11 @@ typedef struct {
 /* Create a single periodic box (eq. lbe on an nx*ny*nz torus).
  * dims = {nx, ny, nz}, each >= 1; D2Q9 requires nz == 1.  nx and the total
  * number of sites must be below 2^31, ny and nz at most 65535; in a batch
- * every box holds less than 2 GiB of populations.  tau: relaxation time,
- * finite and > 1/2 (viscosity T0 (tau - 1/2)).  No device memory for the
- * populations is allocated until lbm_init / lbm_set_state, unless bound with
- * lbm_bind_state.  Errors: LBM_EINVAL, LBM_ENODEV, LBM_EDEVICE, LBM_ENOMEM. */
+ * every box holds less than 2 GiB of populations and has nx at most 2^21.
+ * tau: relaxation time, finite and > 1/2 (viscosity T0 (tau - 1/2)).  No
+ * device memory for the populations is allocated until lbm_init /
+ * lbm_set_state, unless bound with lbm_bind_state.  Errors: LBM_EINVAL,
+ * LBM_ENODEV, LBM_EDEVICE, LBM_ENOMEM. */
 lbm_status lbm_create(lbm_t* out, int32_t lattice, const int64_t dims[3], double tau, int32_t dtype);
 
 /* Create nbox independent periodic boxes advanced together by one launch per

@@ -237,6 +237,8 @@ lbm_status build_tiles(lbm_ctx* h)
         t.mem = h->mem[b];
         t.omega = 1.0 - 1.0 / h->tau[b];
         t.box = b;
+        t.inv_nx = float(1.0 / double(nx));
+        t.inv_ny = float(1.0 / double(ny));
         for (int64_t l0 = 0; l0 < n; l0 += kBlockSites) {
             t.x0 = int(l0 % nx);
             t.y0 = int((l0 / nx) % ny);
@@ -313,11 +315,18 @@ lbm_status create_common(lbm_t* out, int32_t lattice, int32_t nbox, const int64_
                 return fail(LBM_EINVAL, "box %d of a batch must hold less than 2 GiB of populations", b);
             }
         }
-    for (int b = 0; b < nbox; ++b)
+    for (int b = 0; b < nbox; ++b) {
         if (dims[3 * b + 1] > 65535 || dims[3 * b + 2] > 65535) {
             delete h;
             return fail(LBM_EINVAL, "box %d: ny and nz must be at most 65535", b);
         }
+        // the batched step splits a lane's site with a float reciprocal,
+        // exact while x0 + 64 stays below 2^22
+        if (nbox > 1 && dims[3 * b] > (int64_t(1) << 21)) {
+            delete h;
+            return fail(LBM_EINVAL, "box %d of a batch: nx must be at most 2^21", b);
+        }
+    }
 
     auto cleanup = [&](lbm_status s) {
         free_all(h);

@@ -48,6 +48,7 @@ struct alignas(64) TileDesc {
     long long mem;        // element offset of the box's populations
     double omega;         // 1 - 1/tau of the box
     int box;
+    float inv_nx, inv_ny; // 1 / nx, 1 / ny, for the lane -> (x, y, z) split
 };
 static_assert(sizeof(TileDesc) == 64, "tile descriptor is one scalar load");
 

@@ -1,8 +1,9 @@
 // HIP kernels for gfx950 (MI355X) around the step: initialisation, moments,
 // FP64 reductions and a copy kernel used to calibrate bandwidth measurements.
-// The step kernels are in step.hip (single box) and step_batch.hip (batch).
+// The step kernels are in step.hpp (single box) and step_batch.hpp (batch).
 //
-// Data layout: row-tiled structure of arrays (see internal.hpp).  Two buffers
+// Data layout: blocked structure of arrays, row tiles for a single box and
+// 64-site blocks for a batch (see internal.hpp, BoxDesc).  Two buffers
 // alternate: a step reads one and writes the other, so a step never reads what
 // it writes.  The stored value is G_i = S (f_i - w_i), the deviation from the
 // rest weights in units of the lattice's weight quantum 1/S.

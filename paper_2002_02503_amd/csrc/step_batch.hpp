@@ -49,12 +49,16 @@ __global__ __launch_bounds__(256) void k_step_batch(const S* __restrict__ src, S
     for (int t = int(blockIdx.x) * waves + wave; t < ntiles; t += int(gridDim.x) * waves) {
         const TileDesc b = tiles[t];
         if (lane >= b.count) continue;
-        // the lane's site: l = blk * 64 + lane, from the block's first site on
+        // The lane's site l = blk * 64 + lane, from the block's first site on.
+        // xx < nx + 64 and yy < ny + 64, so (xx + 1/2) / nx is at least
+        // 1/(2 nx) away from an integer while the float rounding of the
+        // product is below (xx + 1/2) 2^-23 < 1/(2 nx) for xx < 2^22 (ny and
+        // nz are at most 65535): the floor is the exact quotient.
         const int xx = b.x0 + lane;
-        const int dy = xx / b.nx;
+        const int dy = int((float(xx) + 0.5f) * b.inv_nx);
         const int x = xx - dy * b.nx;
         const int yy = b.y0 + dy;
-        const int dz = yy / b.ny;
+        const int dz = int((float(yy) + 0.5f) * b.inv_ny);
         const int y = yy - dz * b.ny;
         const int z = b.z0 + dz;
 
@@ -73,7 +77,10 @@ __global__ __launch_bounds__(256) void k_step_batch(const S* __restrict__ src, S
             constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
             constexpr bool nt = (cx == 0 && cy == 0 && cz == 0) || (ALIGNED_ROWS && cx == 0);
             const int l = zo[RR - cz] + yo[RR - cy] + xw[RR - cx];  // source site
-            const S* p = at32(sb, unsigned(((l >> 6) * Q + m) * 64 + (l & 63)));
+            // element (l / 64) Q 64 + m 64 + l % 64, with the constant m 64
+            // left for the instruction's offset field
+            const unsigned e = unsigned(l) + (unsigned(l) >> 6) * unsigned(64 * (Q - 1));
+            const S* p = at32(sb, e) + m * 64;
             if constexpr (nt) g[i] = ST::get_nt(p);
             else g[i] = ST::get(p);
         });

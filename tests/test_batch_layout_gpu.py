@@ -198,3 +198,20 @@ def test_checkpoint_layout_as_documented(lattice, dtype):
     u_dec = np.concatenate(j_dec, axis=1) / r_dec
     assert np.allclose(r_dec, r_lib, rtol=0, atol=1e-13)
     assert np.allclose(u_dec, u_lib.reshape(D, -1), rtol=0, atol=1e-13)
+
+
+def test_batch_box_limits():
+    """A batch box longer than 2^21 sites along x is rejected before any
+    device work (the batched step's site split is exact below that)."""
+    from paper_2002_02503_amd import lbm
+
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.Simulation("D3Q19", [(2 ** 21 + 1, 1, 1), (8, 8, 8)], [0.6, 0.7])
+    assert e.value.name == "LBM_EINVAL"
+    dims = [(2 ** 21, 1, 1), (3, 2, 2)]
+    rho, u = _batch_fields(3, dims, seed=12)
+    rb, ub = _run_batch("D3Q19", dims, [0.6, 0.7], "fp32", rho, u, 3)
+    for k, d in enumerate(dims):
+        r0, u0 = _box_fields(dims, rho, u, k)
+        r1, u1 = run_gpu("D3Q19", d, [0.6, 0.7][k], "fp32", r0, u0, 3)
+        assert np.array_equal(rb[k], r1) and np.array_equal(ub[k], u1), d
