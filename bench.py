@@ -78,15 +78,24 @@ KERNEL_SYMBOLS = {"scalar": "k_step", "row_wave": "k_step_vec", "in_place": "k_s
 
 def measure_box(lattice, dims, tau, dtype, rho, u, steps, warmup, tune=True, **kw):
     """Create, initialise, autotune the launch (outside the timed region, state
-    restored), then time `steps` steps."""
+    restored), then time `steps` steps.  The FP64 totals (lbm_totals) before
+    and after give the mass and momentum drift over all the steps taken."""
+    import numpy as np
+
     from paper_2002_02503_amd import lbm
 
     with lbm.Simulation(lattice, dims, tau, dtype=dtype, **kw) as sim:
         sim.init(rho, u)
+        tot0 = sim.totals()
         if tune:
             sim.tune(steps=10)
         ms = timed_steps(sim, steps, warmup)
+        tot1 = sim.totals()
         info = sim.info()
+    mass = tot0[:, 0]
+    conservation = {"steps": int(info["t"]),
+                    "mass_rel_max": float(np.max(np.abs(tot1[:, 0] - mass) / mass)),
+                    "momentum_rel_max": float(np.max(np.abs(tot1[:, 1:] - tot0[:, 1:]).max(axis=1) / mass))}
     bytes_site = info["bytes_per_site_update"]
     nsites = info["nsites"]
     mlups = nsites / (ms * 1e-3) / 1e6
@@ -94,7 +103,7 @@ def measure_box(lattice, dims, tau, dtype, rho, u, steps, warmup, tune=True, **k
     return {"value": mlups, "unit": "MLUPS", "ms_per_step": ms, "steps": steps,
             "bytes_per_site_update": bytes_site, "nsites": nsites, "achieved_GBs": gbs,
             "roofline_frac": gbs / PEAK_HBM_GBS, "kernel": KERNEL_NAMES[info["kernel"]],
-            "block": info["block"], "grid": info["grid"]}
+            "block": info["block"], "grid": info["grid"], "conservation": conservation}
 
 
 def traffic_per_launch(kernel: str, workload: str = "turbulence256"):
@@ -276,6 +285,7 @@ def main():
                                "tau=0.51, FP32 storage of S(f_i - w_i), Hermite order 3",
                    "lattice": "D3Q19", "dims": [256, 256, 256], "tau": tau, "hermite_order": 3},
         "roofline": roofline,
+        "conservation": head["conservation"],
         "cpu_baseline": cpu,
         "copy_probe": {"bytes_moved": 2 * copy_bytes, "GB_s": copy_gbs, "frac_of_peak": copy_gbs / PEAK_HBM_GBS},
         "frac_of_copy": head["achieved_GBs"] / copy_gbs,
@@ -326,7 +336,7 @@ def batch_only(args):
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "256 D3Q19 boxes, sides 16..64, tau 0.52..1, |U| <= 0.1, Taylor-Green, "
                                    "FP32 storage, Hermite order 3, one launch per step", "nsites": nsites},
-            "roofline": roofline, "cpu_baseline": None,
+            "roofline": roofline, "conservation": m["conservation"], "cpu_baseline": None,
             "copy_probe": {"bytes_moved": 2 * copy_bytes, "GB_s": copy_gbs, "frac_of_peak": copy_gbs / PEAK_HBM_GBS},
             "frac_of_copy": m["achieved_GBs"] / copy_gbs}
     print(json.dumps(line), flush=True)
