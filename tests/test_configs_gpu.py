@@ -214,7 +214,8 @@ def test_batched_256_boxes_fp32():
     """256 independent D3Q19 boxes (sides 16..64, own tau and U), Taylor-Green
     in x-y, FP32, 1000 steps as graph launches: every box keeps its z-invariance
     bit for bit and conserves mass and momentum; 16 boxes match the oracle's
-    nx x ny x 1 runs; a batched box equals the same box run alone."""
+    nx x ny x 1 runs; a batched box equals the same box run alone, bit for
+    bit."""
     boxes = inputs.batch_boxes()
     T0, steps = 1.0 / 3.0, 1000
     dims = [b["dims"] for b in boxes]
@@ -253,6 +254,5 @@ def test_batched_256_boxes_fp32():
         with lbm.Simulation("D3Q19", boxes[k]["dims"], boxes[k]["tau"], dtype="fp32") as one:
             one.init(fields[k][0], fields[k][1]).step(steps)
             r1, u1 = one.moments()
-        d = float(np.abs(u1 - ub[k]).max())
-        print(f"box {k}: batched vs alone max |du| = {d:.1e}", flush=True)
-        assert d < 1e-7
+        # the batched and single-box kernels compute the same bits
+        assert np.array_equal(u1, ub[k]) and np.array_equal(r1, rb[k]), k
