@@ -138,6 +138,18 @@ def traffic_per_launch(kernel: str, workload: str = "turbulence256"):
     return float(t["traffic_bytes_per_launch"]), "rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-calibrated"
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (first entry of /proc/cpuinfo), or "unknown"."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline_leg(rho, u, tau, budget_s: float, dtypes):
     """The FP64 oracle as it stands, on the full 256^3 box, for as many steps as
     fit in about `budget_s` seconds of host time -- timed as the CPU baseline.
@@ -171,7 +183,8 @@ def cpu_baseline_leg(rho, u, tau, budget_s: float, dtypes):
     nsites = 256 ** 3
     base = {"value": nsites * steps / wall / 1e6, "unit": "MLUPS", "cores": oracle.get_threads(), "kind": "oracle",
             "sample": f"{steps} step(s) of the full 256^3 D3Q19 turbulence box, FP64 oracle "
-                      f"(literal Hermite-tensor mode, OpenMP), {wall:.1f} s stepping + {t_init:.1f} s init"}
+                      f"(literal Hermite-tensor mode, OpenMP), {wall:.1f} s stepping + {t_init:.1f} s init",
+            "cpu_model": cpu_model()}
     r_ref, u_ref = sim.moments()
     del sim
     errors = {}
