@@ -20,3 +20,31 @@ def test_bench_help_lists_the_workloads():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 0
     assert "turbulence256" in r.stdout and "batch256" in r.stdout
+
+
+def test_traffic_counters_apply_only_to_the_sources_they_were_taken_on(tmp_path, monkeypatch):
+    """bench.traffic_per_launch returns the committed FETCH+WRITE bytes only
+    while the kernel sources hash to the value recorded with them."""
+    import json
+
+    import bench
+
+    f = tmp_path / "traffic.json"
+    json.dump({"source_hash": "abc", "traffic_bytes_per_launch": 123.0}, open(f, "w"))
+    monkeypatch.setattr(bench, "traffic_file", lambda kernel, workload="turbulence256": str(f))
+    monkeypatch.setattr(bench, "source_hash", lambda: "abc")
+    assert bench.traffic_per_launch("scalar")[0] == 123.0
+    monkeypatch.setattr(bench, "source_hash", lambda: "def")
+    value, why = bench.traffic_per_launch("scalar")
+    assert value is None and "changed" in why
+    monkeypatch.setattr(bench, "traffic_file", lambda kernel, workload="turbulence256": str(tmp_path / "none.json"))
+    assert bench.traffic_per_launch("scalar")[0] is None
+
+
+def test_source_hash_covers_the_device_sources():
+    import bench
+
+    names = bench._kernel_sources()
+    assert "csrc/step.hpp" in names and "csrc/step_batch.hpp" in names and "csrc/collide.hpp" in names
+    assert "build.py" in names and "csrc/api.hip" not in names
+    assert len(bench.source_hash()) == 16
