@@ -100,6 +100,27 @@ def test_d3q19_shear_wave_128_fp32():
     assert gal["bgk3"] < 1e-3
 
 
+def test_d3q19_galilean_128_fp64():
+    """The Galilean test of the shear wave on U = (0.1, 0.05, 0) at 128^3 in
+    FP64, where rounding no longer limits the rate fit: the paper's operator
+    (K = 3) and the zero-velocity filter (K = 2) change the decay rate by the
+    same relative amounts as the oracle's runs of the same flow, about 1e-5
+    against 3e-2."""
+    n, tau, steps, U = 128, 0.55, 2000, (0.1, 0.05, 0.0)
+    gal_gpu, gal_ora = {}, {}
+    for K in (3, 2):
+        _, _, tU, aU = _shear_gpu("D3Q19", (n, n, n), tau, U, steps, dtype="fp64", K=K)
+        _, _, t0, a0 = _shear_gpu("D3Q19", (n, n, n), tau, (0.0, 0.0, 0.0), steps, dtype="fp64", K=K)
+        gal_gpu[K] = fit_decay(tU, aU) / fit_decay(t0, a0) - 1
+        gal_ora[K] = (_shear_oracle_rate("D3Q19", n, tau, U, steps, K=K)
+                      / _shear_oracle_rate("D3Q19", n, tau, (0.0, 0.0, 0.0), steps, K=K) - 1)
+    print(f"Galilean error FP64 128^3: K=3 GPU {gal_gpu[3]:.3e} oracle {gal_ora[3]:.3e}; "
+          f"K=2 GPU {gal_gpu[2]:.3e} oracle {gal_ora[2]:.3e}", flush=True)
+    for K in (3, 2):
+        assert abs(gal_gpu[K] - gal_ora[K]) < 1e-8, K
+    assert abs(gal_gpu[3]) < 3e-5 and abs(gal_gpu[2]) > 1e-2
+
+
 def test_d3q39_shear_wave_192_fp32():
     """D3Q39 (K = 4), 192^3, FP32, tau = 0.6, shear wave on U = (0.2, 0, 0),
     1000 steps: parity with the oracle, and a smaller Galilean error than
