@@ -278,107 +278,115 @@ lbm_status create_common(lbm_t* out, int32_t lattice, int32_t nbox, const int64_
     if (st != LBM_OK) return st;
 
     lbm_ctx* h = new lbm_ctx();
-    h->lattice = lattice;
-    h->dtype = dtype;
-    h->lat = L;
-    h->K = L.k_default;
-    h->nbox = nbox;
-    h->dims.assign(dims, dims + 3 * nbox);
-    h->tau.assign(tau, tau + nbox);
-    h->offset.resize(nbox);
-    h->mem.resize(nbox);
-    h->device = dev;
-    // A single box is stored in row tiles (blocks of w = nx sites); the boxes
-    // of a batch in blocks of 64 sites, each box padded to whole blocks.
-    int64_t off = 0, stored = 0;
-    bool aligned = true;
-    for (int b = 0; b < nbox; ++b) {
-        const int64_t n = dims[3 * b] * dims[3 * b + 1] * dims[3 * b + 2];
-        h->offset[b] = off;
-        h->mem[b] = stored * L.Q;
-        off += n;
-        stored += (nbox == 1) ? n : (n + kBlockSites - 1) / kBlockSites * kBlockSites;
-        aligned = aligned && dims[3 * b] % kBlockSites == 0;
-    }
-    h->nsites = off;
-    h->nstored = stored;
-    h->aligned_rows = aligned;
-    h->elem = storage_bytes(dtype);
-    // Q * nstored elements, allocation rounded to 256 bytes
-    h->state_bytes = ((size_t(h->nstored) * size_t(L.Q) * h->elem + 255) / 256) * 256;
-    if (nbox > 1)
+    // an exception (host allocation) past this point frees the handle
+    // before the entry point's guard turns it into an error code
+    try {
+        h->lattice = lattice;
+        h->dtype = dtype;
+        h->lat = L;
+        h->K = L.k_default;
+        h->nbox = nbox;
+        h->dims.assign(dims, dims + 3 * nbox);
+        h->tau.assign(tau, tau + nbox);
+        h->offset.resize(nbox);
+        h->mem.resize(nbox);
+        h->device = dev;
+        // A single box is stored in row tiles (blocks of w = nx sites); the boxes
+        // of a batch in blocks of 64 sites, each box padded to whole blocks.
+        int64_t off = 0, stored = 0;
+        bool aligned = true;
         for (int b = 0; b < nbox; ++b) {
-            const uint64_t nb = uint64_t(dims[3 * b]) * uint64_t(dims[3 * b + 1]) * uint64_t(dims[3 * b + 2]);
-            const uint64_t padded = (nb + kBlockSites - 1) / kBlockSites * kBlockSites;
-            if (padded * uint64_t(L.Q) * h->elem >= (uint64_t(1) << 31)) {
+            const int64_t n = dims[3 * b] * dims[3 * b + 1] * dims[3 * b + 2];
+            h->offset[b] = off;
+            h->mem[b] = stored * L.Q;
+            off += n;
+            stored += (nbox == 1) ? n : (n + kBlockSites - 1) / kBlockSites * kBlockSites;
+            aligned = aligned && dims[3 * b] % kBlockSites == 0;
+        }
+        h->nsites = off;
+        h->nstored = stored;
+        h->aligned_rows = aligned;
+        h->elem = storage_bytes(dtype);
+        // Q * nstored elements, allocation rounded to 256 bytes
+        h->state_bytes = ((size_t(h->nstored) * size_t(L.Q) * h->elem + 255) / 256) * 256;
+        if (nbox > 1)
+            for (int b = 0; b < nbox; ++b) {
+                const uint64_t nb = uint64_t(dims[3 * b]) * uint64_t(dims[3 * b + 1]) * uint64_t(dims[3 * b + 2]);
+                const uint64_t padded = (nb + kBlockSites - 1) / kBlockSites * kBlockSites;
+                if (padded * uint64_t(L.Q) * h->elem >= (uint64_t(1) << 31)) {
+                    delete h;
+                    return fail(LBM_EINVAL, "box %d of a batch must hold less than 2 GiB of populations", b);
+                }
+            }
+        for (int b = 0; b < nbox; ++b) {
+            if (dims[3 * b + 1] > 65535 || dims[3 * b + 2] > 65535) {
                 delete h;
-                return fail(LBM_EINVAL, "box %d of a batch must hold less than 2 GiB of populations", b);
+                return fail(LBM_EINVAL, "box %d: ny and nz must be at most 65535", b);
+            }
+            // the batched step splits a lane's site with a float reciprocal,
+            // exact while x0 + 64 stays below 2^22
+            if (nbox > 1 && dims[3 * b] > (int64_t(1) << 21)) {
+                delete h;
+                return fail(LBM_EINVAL, "box %d of a batch: nx must be at most 2^21", b);
             }
         }
-    for (int b = 0; b < nbox; ++b) {
-        if (dims[3 * b + 1] > 65535 || dims[3 * b + 2] > 65535) {
-            delete h;
-            return fail(LBM_EINVAL, "box %d: ny and nz must be at most 65535", b);
-        }
-        // the batched step splits a lane's site with a float reciprocal,
-        // exact while x0 + 64 stays below 2^22
-        if (nbox > 1 && dims[3 * b] > (int64_t(1) << 21)) {
-            delete h;
-            return fail(LBM_EINVAL, "box %d of a batch: nx must be at most 2^21", b);
-        }
-    }
 
-    auto cleanup = [&](lbm_status s) {
+        auto cleanup = [&](lbm_status s) {
+            free_all(h);
+            delete h;
+            return s;
+        };
+        hipError_t e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return cleanup(fail_hip(e, "hipStreamCreate"));
+
+        // reduction chunks (never straddle two boxes)
+        std::vector<ChunkDesc> chunks;
+        std::vector<int> begin;
+        for (int b = 0; b < nbox; ++b) {
+            begin.push_back(int(chunks.size()));
+            const int64_t n = dims[3 * b] * dims[3 * b + 1] * dims[3 * b + 2];
+            for (int64_t s = 0; s < n; s += kChunkSites) {
+                const int64_t cnt = (n - s < kChunkSites) ? (n - s) : kChunkSites;
+                chunks.push_back({h->offset[b] + s, int(cnt), b});
+            }
+        }
+        begin.push_back(int(chunks.size()));
+        h->nchunks = int(chunks.size());
+        if ((e = hipMalloc(&h->d_chunks, chunks.size() * sizeof(ChunkDesc))) != hipSuccess ||
+            (e = hipMalloc(&h->d_box_chunk_begin, begin.size() * sizeof(int))) != hipSuccess ||
+            (e = hipMalloc(&h->d_partial, chunks.size() * 4 * sizeof(double))) != hipSuccess ||
+            (e = hipMalloc(&h->d_out, size_t(nbox) * 4 * sizeof(double))) != hipSuccess)
+            return cleanup(fail_hip(e, "hipMalloc(reduction tables)"));
+        if ((e = hipMemcpy(h->d_chunks, chunks.data(), chunks.size() * sizeof(ChunkDesc), hipMemcpyHostToDevice)) !=
+                hipSuccess ||
+            (e = hipMemcpy(h->d_box_chunk_begin, begin.data(), begin.size() * sizeof(int), hipMemcpyHostToDevice)) !=
+                hipSuccess)
+            return cleanup(fail_hip(e, "copy reduction tables"));
+
+        {
+            std::vector<BoxDesc> boxes(nbox);
+            for (int b = 0; b < nbox; ++b) {
+                boxes[b].nx = int(dims[3 * b]);
+                boxes[b].ny = int(dims[3 * b + 1]);
+                boxes[b].nz = int(dims[3 * b + 2]);
+                boxes[b].w = (nbox == 1) ? boxes[b].nx : kBlockSites;
+                boxes[b].offset = h->offset[b];
+                boxes[b].mem = h->mem[b];
+                boxes[b].omega = 1.0 - 1.0 / tau[b];
+            }
+            if ((e = hipMalloc(&h->d_boxes, boxes.size() * sizeof(BoxDesc))) != hipSuccess)
+                return cleanup(fail_hip(e, "hipMalloc(boxes)"));
+            if ((e = hipMemcpy(h->d_boxes, boxes.data(), boxes.size() * sizeof(BoxDesc), hipMemcpyHostToDevice)) !=
+                hipSuccess)
+                return cleanup(fail_hip(e, "copy boxes"));
+        }
+        *out = h;
+        return LBM_OK;
+    } catch (...) {
         free_all(h);
         delete h;
-        return s;
-    };
-    hipError_t e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
-    if (e != hipSuccess) return cleanup(fail_hip(e, "hipStreamCreate"));
-
-    // reduction chunks (never straddle two boxes)
-    std::vector<ChunkDesc> chunks;
-    std::vector<int> begin;
-    for (int b = 0; b < nbox; ++b) {
-        begin.push_back(int(chunks.size()));
-        const int64_t n = dims[3 * b] * dims[3 * b + 1] * dims[3 * b + 2];
-        for (int64_t s = 0; s < n; s += kChunkSites) {
-            const int64_t cnt = (n - s < kChunkSites) ? (n - s) : kChunkSites;
-            chunks.push_back({h->offset[b] + s, int(cnt), b});
-        }
+        throw;
     }
-    begin.push_back(int(chunks.size()));
-    h->nchunks = int(chunks.size());
-    if ((e = hipMalloc(&h->d_chunks, chunks.size() * sizeof(ChunkDesc))) != hipSuccess ||
-        (e = hipMalloc(&h->d_box_chunk_begin, begin.size() * sizeof(int))) != hipSuccess ||
-        (e = hipMalloc(&h->d_partial, chunks.size() * 4 * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc(&h->d_out, size_t(nbox) * 4 * sizeof(double))) != hipSuccess)
-        return cleanup(fail_hip(e, "hipMalloc(reduction tables)"));
-    if ((e = hipMemcpy(h->d_chunks, chunks.data(), chunks.size() * sizeof(ChunkDesc), hipMemcpyHostToDevice)) !=
-            hipSuccess ||
-        (e = hipMemcpy(h->d_box_chunk_begin, begin.data(), begin.size() * sizeof(int), hipMemcpyHostToDevice)) !=
-            hipSuccess)
-        return cleanup(fail_hip(e, "copy reduction tables"));
-
-    {
-        std::vector<BoxDesc> boxes(nbox);
-        for (int b = 0; b < nbox; ++b) {
-            boxes[b].nx = int(dims[3 * b]);
-            boxes[b].ny = int(dims[3 * b + 1]);
-            boxes[b].nz = int(dims[3 * b + 2]);
-            boxes[b].w = (nbox == 1) ? boxes[b].nx : kBlockSites;
-            boxes[b].offset = h->offset[b];
-            boxes[b].mem = h->mem[b];
-            boxes[b].omega = 1.0 - 1.0 / tau[b];
-        }
-        if ((e = hipMalloc(&h->d_boxes, boxes.size() * sizeof(BoxDesc))) != hipSuccess)
-            return cleanup(fail_hip(e, "hipMalloc(boxes)"));
-        if ((e = hipMemcpy(h->d_boxes, boxes.data(), boxes.size() * sizeof(BoxDesc), hipMemcpyHostToDevice)) !=
-            hipSuccess)
-            return cleanup(fail_hip(e, "copy boxes"));
-    }
-    *out = h;
-    return LBM_OK;
 }
 
 lbm_status alloc_buffer(lbm_ctx* h, int k)
@@ -572,186 +580,264 @@ extern "C" {
 
 lbm_status lbm_create(lbm_t* out, int32_t lattice, const int64_t dims[3], double tau, int32_t dtype)
 {
-    return create_common(out, lattice, 1, dims, &tau, dtype);
+    try {
+        return create_common(out, lattice, 1, dims, &tau, dtype);
+    } catch (const std::bad_alloc&) {
+        return fail(LBM_ENOMEM, "lbm_create: host memory allocation failed");
+    } catch (...) {
+        return fail(LBM_EDEVICE, "lbm_create: unexpected host exception");
+    }
 }
 
 lbm_status lbm_create_batch(lbm_t* out, int32_t lattice, int32_t nbox, const int64_t* dims, const double* tau,
                             int32_t dtype)
 {
-    return create_common(out, lattice, nbox, dims, tau, dtype);
+    try {
+        return create_common(out, lattice, nbox, dims, tau, dtype);
+    } catch (const std::bad_alloc&) {
+        return fail(LBM_ENOMEM, "lbm_create_batch: host memory allocation failed");
+    } catch (...) {
+        return fail(LBM_EDEVICE, "lbm_create_batch: unexpected host exception");
+    }
 }
 
 lbm_status lbm_set_hermite_order(lbm_t h, int32_t K)
 {
-    if (lbm_status st = check_handle(h)) return st;
-    if (K < 2 || K > h->lat.k_max)
-        return fail(LBM_EINVAL, "Hermite order K = %d outside [2, 2N-1 = %d]", K, h->lat.k_max);
-    if (K < 3 && h->theta != 0.0)
-        return fail(LBM_EINVAL, "the energy-flux term (theta != 0) needs K >= 3");
-    if (h->initialized) return fail(LBM_ESTATE, "set the Hermite order before lbm_init");
-    h->K = K;
-    drop_graphs(h);
-    return LBM_OK;
+    try {
+        if (lbm_status st = check_handle(h)) return st;
+        if (K < 2 || K > h->lat.k_max)
+            return fail(LBM_EINVAL, "Hermite order K = %d outside [2, 2N-1 = %d]", K, h->lat.k_max);
+        if (K < 3 && h->theta != 0.0)
+            return fail(LBM_EINVAL, "the energy-flux term (theta != 0) needs K >= 3");
+        if (h->initialized) return fail(LBM_ESTATE, "set the Hermite order before lbm_init");
+        h->K = K;
+        drop_graphs(h);
+        return LBM_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(LBM_ENOMEM, "lbm_set_hermite_order: host memory allocation failed");
+    } catch (...) {
+        return fail(LBM_EDEVICE, "lbm_set_hermite_order: unexpected host exception");
+    }
 }
 
 lbm_status lbm_set_collision(lbm_t h, int32_t collision, double theta)
 {
-    if (lbm_status st = check_handle(h)) return st;
-    if (collision != LBM_COLLISION_FILTERED && collision != LBM_COLLISION_BGK)
-        return fail(LBM_EINVAL, "unknown collision operator %d", collision);
-    if (!std::isfinite(theta)) return fail(LBM_EINVAL, "theta must be finite");
-    if (theta != 0.0 && collision != LBM_COLLISION_FILTERED)
-        return fail(LBM_EINVAL, "the energy-flux term (theta != 0) belongs to the filtered operator");
-    if (theta != 0.0 && h->K < 3) return fail(LBM_EINVAL, "the energy-flux term (theta != 0) needs K >= 3");
-    if (h->initialized) return fail(LBM_ESTATE, "set the collision operator before lbm_init");
-    h->collision = collision;
-    h->theta = theta;
-    drop_graphs(h);
-    return LBM_OK;
+    try {
+        if (lbm_status st = check_handle(h)) return st;
+        if (collision != LBM_COLLISION_FILTERED && collision != LBM_COLLISION_BGK)
+            return fail(LBM_EINVAL, "unknown collision operator %d", collision);
+        if (!std::isfinite(theta)) return fail(LBM_EINVAL, "theta must be finite");
+        if (theta != 0.0 && collision != LBM_COLLISION_FILTERED)
+            return fail(LBM_EINVAL, "the energy-flux term (theta != 0) belongs to the filtered operator");
+        if (theta != 0.0 && h->K < 3) return fail(LBM_EINVAL, "the energy-flux term (theta != 0) needs K >= 3");
+        if (h->initialized) return fail(LBM_ESTATE, "set the collision operator before lbm_init");
+        h->collision = collision;
+        h->theta = theta;
+        drop_graphs(h);
+        return LBM_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(LBM_ENOMEM, "lbm_set_collision: host memory allocation failed");
+    } catch (...) {
+        return fail(LBM_EDEVICE, "lbm_set_collision: unexpected host exception");
+    }
 }
 
 lbm_status lbm_set_stream(lbm_t h, void* hip_stream)
 {
-    if (lbm_status st = check_handle(h)) return st;
-    h->stream = static_cast<hipStream_t>(hip_stream);
-    return LBM_OK;
+    try {
+        if (lbm_status st = check_handle(h)) return st;
+        h->stream = static_cast<hipStream_t>(hip_stream);
+        return LBM_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(LBM_ENOMEM, "lbm_set_stream: host memory allocation failed");
+    } catch (...) {
+        return fail(LBM_EDEVICE, "lbm_set_stream: unexpected host exception");
+    }
 }
 
 lbm_status lbm_state_bytes(lbm_t h, size_t* bytes_each)
 {
-    if (lbm_status st = check_handle(h)) return st;
-    if (!bytes_each) return fail(LBM_EINVAL, "bytes_each is NULL");
-    *bytes_each = h->state_bytes;
-    return LBM_OK;
+    try {
+        if (lbm_status st = check_handle(h)) return st;
+        if (!bytes_each) return fail(LBM_EINVAL, "bytes_each is NULL");
+        *bytes_each = h->state_bytes;
+        return LBM_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(LBM_ENOMEM, "lbm_state_bytes: host memory allocation failed");
+    } catch (...) {
+        return fail(LBM_EDEVICE, "lbm_state_bytes: unexpected host exception");
+    }
 }
 
 lbm_status lbm_bind_state(lbm_t h, void* buf_a, void* buf_b, size_t bytes_each)
 {
-    if (lbm_status st = check_handle(h)) return st;
-    if (!buf_a || !buf_b || buf_a == buf_b) return fail(LBM_EINVAL, "need two distinct non-NULL buffers");
-    if (bytes_each < h->state_bytes)
-        return fail(LBM_EINVAL, "buffers hold %zu bytes, need %zu", bytes_each, h->state_bytes);
-    if ((reinterpret_cast<uintptr_t>(buf_a) | reinterpret_cast<uintptr_t>(buf_b)) & 255u)
-        return fail(LBM_EINVAL, "buffers must be 256-byte aligned");
-    if (h->initialized || h->buf[0]) return fail(LBM_ESTATE, "bind buffers before lbm_init / lbm_set_state");
-    h->buf[0] = buf_a;
-    h->buf[1] = buf_b;
-    h->owns_buf = false;
-    h->bound = true;
-    return LBM_OK;
+    try {
+        if (lbm_status st = check_handle(h)) return st;
+        if (!buf_a || !buf_b || buf_a == buf_b) return fail(LBM_EINVAL, "need two distinct non-NULL buffers");
+        if (bytes_each < h->state_bytes)
+            return fail(LBM_EINVAL, "buffers hold %zu bytes, need %zu", bytes_each, h->state_bytes);
+        if ((reinterpret_cast<uintptr_t>(buf_a) | reinterpret_cast<uintptr_t>(buf_b)) & 255u)
+            return fail(LBM_EINVAL, "buffers must be 256-byte aligned");
+        if (h->initialized || h->buf[0]) return fail(LBM_ESTATE, "bind buffers before lbm_init / lbm_set_state");
+        h->buf[0] = buf_a;
+        h->buf[1] = buf_b;
+        h->owns_buf = false;
+        h->bound = true;
+        return LBM_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(LBM_ENOMEM, "lbm_bind_state: host memory allocation failed");
+    } catch (...) {
+        return fail(LBM_EDEVICE, "lbm_bind_state: unexpected host exception");
+    }
 }
 
 lbm_status lbm_set_graph_chunk(lbm_t h, int32_t steps)
 {
-    if (lbm_status st = check_handle(h)) return st;
-    if (steps < 1 || steps > 4096) return fail(LBM_EINVAL, "graph chunk must be in [1, 4096]");
-    h->graph_chunk = steps;
-    return LBM_OK;
+    try {
+        if (lbm_status st = check_handle(h)) return st;
+        if (steps < 1 || steps > 4096) return fail(LBM_EINVAL, "graph chunk must be in [1, 4096]");
+        h->graph_chunk = steps;
+        return LBM_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(LBM_ENOMEM, "lbm_set_graph_chunk: host memory allocation failed");
+    } catch (...) {
+        return fail(LBM_EDEVICE, "lbm_set_graph_chunk: unexpected host exception");
+    }
 }
 
 lbm_status lbm_set_launch(lbm_t h, int32_t block, int32_t grid)
 {
-    if (lbm_status st = check_handle(h)) return st;
-    if (!(block == 0 || block == 64 || block == 128 || block == 256))
-        return fail(LBM_EINVAL, "block must be 0, 64, 128 or 256");
-    if (grid < 0) return fail(LBM_EINVAL, "grid must be >= 0");
-    if (h->initialized) return fail(LBM_ESTATE, "set the launch shape before lbm_init");
-    h->block = block;
-    h->grid = grid;
-    drop_graphs(h);
-    return LBM_OK;
+    try {
+        if (lbm_status st = check_handle(h)) return st;
+        if (!(block == 0 || block == 64 || block == 128 || block == 256))
+            return fail(LBM_EINVAL, "block must be 0, 64, 128 or 256");
+        if (grid < 0) return fail(LBM_EINVAL, "grid must be >= 0");
+        if (h->initialized) return fail(LBM_ESTATE, "set the launch shape before lbm_init");
+        h->block = block;
+        h->grid = grid;
+        drop_graphs(h);
+        return LBM_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(LBM_ENOMEM, "lbm_set_launch: host memory allocation failed");
+    } catch (...) {
+        return fail(LBM_EDEVICE, "lbm_set_launch: unexpected host exception");
+    }
 }
 
 lbm_status lbm_set_kernel(lbm_t h, int32_t kernel)
 {
-    if (lbm_status st = check_handle(h)) return st;
-    if (kernel != LBM_KERNEL_AUTO && kernel != LBM_KERNEL_SCALAR && kernel != LBM_KERNEL_ROW_WAVE &&
-        kernel != LBM_KERNEL_IN_PLACE && kernel != LBM_KERNEL_TWO_ROW)
-        return fail(LBM_EINVAL, "unknown kernel variant %d", kernel);
-    if (kernel == LBM_KERNEL_IN_PLACE && !is_single(h))
-        return fail(LBM_EINVAL, "the in-place step is for a single box; batches use the tiled batched kernel");
-    if (kernel == LBM_KERNEL_TWO_ROW && (!is_single(h) || h->dims[1] % 2 != 0))
-        return fail(LBM_EINVAL, "the two-row step needs a single box with ny even");
-    if (kernel == LBM_KERNEL_ROW_WAVE && !row_wave_sites(h))
-        return fail(LBM_EINVAL, "the row-wave step needs a single box with nx a multiple of the sites per lane "
-                                "and at most 64 lanes per row");
-    // on an initialised handle the state first goes to the natural layout in
-    // buf[0], where every kernel can start
-    if (lbm_status st = canonicalize(h)) return st;
-    h->kernel = kernel;
-    drop_graphs(h);
-    return LBM_OK;
+    try {
+        if (lbm_status st = check_handle(h)) return st;
+        if (kernel != LBM_KERNEL_AUTO && kernel != LBM_KERNEL_SCALAR && kernel != LBM_KERNEL_ROW_WAVE &&
+            kernel != LBM_KERNEL_IN_PLACE && kernel != LBM_KERNEL_TWO_ROW)
+            return fail(LBM_EINVAL, "unknown kernel variant %d", kernel);
+        if (kernel == LBM_KERNEL_IN_PLACE && !is_single(h))
+            return fail(LBM_EINVAL, "the in-place step is for a single box; batches use the tiled batched kernel");
+        if (kernel == LBM_KERNEL_TWO_ROW && (!is_single(h) || h->dims[1] % 2 != 0))
+            return fail(LBM_EINVAL, "the two-row step needs a single box with ny even");
+        if (kernel == LBM_KERNEL_ROW_WAVE && !row_wave_sites(h))
+            return fail(LBM_EINVAL, "the row-wave step needs a single box with nx a multiple of the sites per lane "
+                                    "and at most 64 lanes per row");
+        // on an initialised handle the state first goes to the natural layout in
+        // buf[0], where every kernel can start
+        if (lbm_status st = canonicalize(h)) return st;
+        h->kernel = kernel;
+        drop_graphs(h);
+        return LBM_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(LBM_ENOMEM, "lbm_set_kernel: host memory allocation failed");
+    } catch (...) {
+        return fail(LBM_EDEVICE, "lbm_set_kernel: unexpected host exception");
+    }
 }
 
 lbm_status lbm_init(lbm_t h, const double* rho, const double* u, int32_t on_device)
 {
-    if (lbm_status st = check_handle(h)) return st;
-    if (!rho || !u) return fail(LBM_EINVAL, "rho or u is NULL");
-    HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
-    if (lbm_status st = ensure_buffers(h)) return st;
-    if (lbm_status st = build_tiles(h)) return st;
-    if (lbm_status st = clear_padding(h)) return st;
-    const size_t n = size_t(h->nsites);
-    double *drho = nullptr, *du = nullptr;
-    bool t1 = false, t2 = false;
-    if (lbm_status st = stage_in(rho, n, on_device, h->stream, &drho, &t1)) return st;
-    if (lbm_status st = stage_in(u, n * h->lat.D, on_device, h->stream, &du, &t2)) {
+    try {
+        if (lbm_status st = check_handle(h)) return st;
+        if (!rho || !u) return fail(LBM_EINVAL, "rho or u is NULL");
+        HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+        if (lbm_status st = ensure_buffers(h)) return st;
+        if (lbm_status st = build_tiles(h)) return st;
+        if (lbm_status st = clear_padding(h)) return st;
+        const size_t n = size_t(h->nsites);
+        double *drho = nullptr, *du = nullptr;
+        bool t1 = false, t2 = false;
+        if (lbm_status st = stage_in(rho, n, on_device, h->stream, &drho, &t1)) return st;
+        if (lbm_status st = stage_in(u, n * h->lat.D, on_device, h->stream, &du, &t2)) {
+            if (t1) (void)hipFree(drho);
+            return st;
+        }
+        hipError_t e = launch_init(h->lattice, h->dtype, h->K, drho, du, h->buf[0], h->d_chunks, h->nchunks, h->d_boxes,
+                                   h->nsites, h->stream);
+        hipError_t e2 = hipStreamSynchronize(h->stream);
         if (t1) (void)hipFree(drho);
-        return st;
+        if (t2) (void)hipFree(du);
+        if (e != hipSuccess) return fail_hip(e, "init kernel");
+        if (e2 != hipSuccess) return fail_hip(e2, "init synchronize");
+        h->cur = 0;
+        h->t = 0;
+        h->initialized = true;
+        return LBM_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(LBM_ENOMEM, "lbm_init: host memory allocation failed");
+    } catch (...) {
+        return fail(LBM_EDEVICE, "lbm_init: unexpected host exception");
     }
-    hipError_t e = launch_init(h->lattice, h->dtype, h->K, drho, du, h->buf[0], h->d_chunks, h->nchunks, h->d_boxes,
-                               h->nsites, h->stream);
-    hipError_t e2 = hipStreamSynchronize(h->stream);
-    if (t1) (void)hipFree(drho);
-    if (t2) (void)hipFree(du);
-    if (e != hipSuccess) return fail_hip(e, "init kernel");
-    if (e2 != hipSuccess) return fail_hip(e2, "init synchronize");
-    h->cur = 0;
-    h->t = 0;
-    h->initialized = true;
-    return LBM_OK;
 }
 
 lbm_status lbm_prepare(lbm_t h)
 {
-    if (lbm_status st = check_handle(h)) return st;
-    if (!h->initialized) return fail(LBM_ESTATE, "lbm_prepare before lbm_init");
-    HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
-    if (!in_place(h))
-        if (lbm_status st = ensure_second(h)) return st;
-    for (int p = 0; p < 2; ++p)
-        if (lbm_status st = build_graph(h, p)) return st;
-    return LBM_OK;
+    try {
+        if (lbm_status st = check_handle(h)) return st;
+        if (!h->initialized) return fail(LBM_ESTATE, "lbm_prepare before lbm_init");
+        HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+        if (!in_place(h))
+            if (lbm_status st = ensure_second(h)) return st;
+        for (int p = 0; p < 2; ++p)
+            if (lbm_status st = build_graph(h, p)) return st;
+        return LBM_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(LBM_ENOMEM, "lbm_prepare: host memory allocation failed");
+    } catch (...) {
+        return fail(LBM_EDEVICE, "lbm_prepare: unexpected host exception");
+    }
 }
 
 lbm_status lbm_step(lbm_t h, int64_t n)
 {
-    if (lbm_status st = check_handle(h)) return st;
-    if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
-    if (!h->initialized) return fail(LBM_ESTATE, "lbm_step before lbm_init");
-    if (n == 0) return LBM_OK;
-    HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
-    if (!in_place(h))
-        if (lbm_status st = ensure_second(h)) return st;
-    if (lbm_status st = build_tiles(h)) return st;
-    const int G = h->graph_chunk;
-    int64_t left = n;
-    if (G > 1) {
-        while (left >= G) {
-            if (lbm_status st = build_graph(h, h->cur)) return st;
-            HIP_TRY(hipGraphLaunch(h->gexec[h->cur], h->stream), "hipGraphLaunch");
-            h->cur ^= (G & 1);
-            h->t += G;
-            left -= G;
+    try {
+        if (lbm_status st = check_handle(h)) return st;
+        if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
+        if (!h->initialized) return fail(LBM_ESTATE, "lbm_step before lbm_init");
+        if (n == 0) return LBM_OK;
+        HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+        if (!in_place(h))
+            if (lbm_status st = ensure_second(h)) return st;
+        if (lbm_status st = build_tiles(h)) return st;
+        const int G = h->graph_chunk;
+        int64_t left = n;
+        if (G > 1) {
+            while (left >= G) {
+                if (lbm_status st = build_graph(h, h->cur)) return st;
+                HIP_TRY(hipGraphLaunch(h->gexec[h->cur], h->stream), "hipGraphLaunch");
+                h->cur ^= (G & 1);
+                h->t += G;
+                left -= G;
+            }
         }
+        for (; left > 0; --left) {
+            hipError_t e = launch_one(h, h->cur, h->stream);
+            if (e != hipSuccess) return fail_hip(e, "step kernel launch");
+            h->cur ^= 1;
+            h->t += 1;
+        }
+        return LBM_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(LBM_ENOMEM, "lbm_step: host memory allocation failed");
+    } catch (...) {
+        return fail(LBM_EDEVICE, "lbm_step: unexpected host exception");
     }
-    for (; left > 0; --left) {
-        hipError_t e = launch_one(h, h->cur, h->stream);
-        if (e != hipSuccess) return fail_hip(e, "step kernel launch");
-        h->cur ^= 1;
-        h->t += 1;
-    }
-    return LBM_OK;
 }
 
 }  // extern "C"
@@ -815,292 +901,352 @@ extern "C" {
 
 lbm_status lbm_tune(lbm_t h, int32_t steps, const char* cache_path)
 {
-    if (lbm_status st = check_handle(h)) return st;
-    if (steps < 1) return fail(LBM_EINVAL, "steps must be >= 1");
-    if (!h->initialized) return fail(LBM_ESTATE, "lbm_tune needs an initialised state");
-    if (!cache_path) cache_path = std::getenv("LBM_TUNE_CACHE");
-    const std::string key = tune_key(h);
-    LaunchChoice best;
-    if (cache_lookup(cache_path, key, &best)) {
-        if (best.kernel == LBM_KERNEL_ROW_WAVE && !row_wave_sites(h)) best.kernel = LBM_KERNEL_SCALAR;
-        if (best.kernel == LBM_KERNEL_IN_PLACE && !is_single(h)) best.kernel = LBM_KERNEL_SCALAR;
-        if (best.kernel == LBM_KERNEL_TWO_ROW && (!is_single(h) || h->dims[1] % 2 != 0))
-            best.kernel = LBM_KERNEL_SCALAR;
-        return apply_choice(h, best);
-    }
-    HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
-
-    std::vector<LaunchChoice> cand;
-    if (is_single(h)) {
-        for (int b : {64, 128, 256}) cand.push_back({LBM_KERNEL_SCALAR, b, 0});
-        cand.push_back({LBM_KERNEL_IN_PLACE, 256, 0});
-        if (h->dims[1] % 2 == 0) cand.push_back({LBM_KERNEL_TWO_ROW, 256, 0});
-        if (row_wave_sites(h)) cand.push_back({LBM_KERNEL_ROW_WAVE, 0, 0});
-    } else {
-        for (int b : {64, 128, 256})
-            for (int g : {0, 1024, 2048, 4096}) cand.push_back({LBM_KERNEL_SCALAR, b, g});
-    }
-
-    // tuning steps the state: keep a copy and restore it afterwards; the
-    // candidates switch kernels, so start from the natural layout in buf[0]
-    if (lbm_status st = canonicalize(h)) return st;
-    const int cur0 = h->cur;
-    const int64_t t0 = h->t;
-    const LaunchChoice old = {h->kernel, h->block, h->grid};
-    void* saved = nullptr;
-    HIP_TRY(hipMalloc(&saved, h->state_bytes), "hipMalloc(tuning copy)");
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipError_t e = hipMemcpyAsync(saved, h->buf[cur0], h->state_bytes, hipMemcpyDeviceToDevice, h->stream);
-    if (e == hipSuccess) e = hipEventCreate(&e0);
-    if (e == hipSuccess) e = hipEventCreate(&e1);
-    lbm_status st = (e == hipSuccess) ? LBM_OK : fail_hip(e, "tuning set-up");
-    // Every candidate is timed in kTuneRounds interleaved rounds and keeps its
-    // fastest round, so a slow window of the device (clock ramp, a neighbour's
-    // traffic) does not decide the choice.
-    std::vector<float> cand_ms(cand.size(), 0.f);
-    for (int round = 0; round < kTuneRounds && st == LBM_OK; ++round) {
-        for (size_t k = 0; k < cand.size() && st == LBM_OK; ++k) {
-            if ((st = apply_choice(h, cand[k])) != LBM_OK) break;
-            if ((st = lbm_step(h, 2)) != LBM_OK) break;
-            if ((e = hipEventRecord(e0, h->stream)) != hipSuccess) { st = fail_hip(e, "hipEventRecord"); break; }
-            if ((st = lbm_step(h, steps)) != LBM_OK) break;
-            if ((e = hipEventRecord(e1, h->stream)) != hipSuccess) { st = fail_hip(e, "hipEventRecord"); break; }
-            if ((e = hipEventSynchronize(e1)) != hipSuccess) { st = fail_hip(e, "hipEventSynchronize"); break; }
-            float ms = 0.f;
-            if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) { st = fail_hip(e, "hipEventElapsedTime"); break; }
-            if (round == 0 || ms < cand_ms[k]) cand_ms[k] = ms;
+    try {
+        if (lbm_status st = check_handle(h)) return st;
+        if (steps < 1) return fail(LBM_EINVAL, "steps must be >= 1");
+        if (!h->initialized) return fail(LBM_ESTATE, "lbm_tune needs an initialised state");
+        if (!cache_path) cache_path = std::getenv("LBM_TUNE_CACHE");
+        const std::string key = tune_key(h);
+        LaunchChoice best;
+        if (cache_lookup(cache_path, key, &best)) {
+            if (best.kernel == LBM_KERNEL_ROW_WAVE && !row_wave_sites(h)) best.kernel = LBM_KERNEL_SCALAR;
+            if (best.kernel == LBM_KERNEL_IN_PLACE && !is_single(h)) best.kernel = LBM_KERNEL_SCALAR;
+            if (best.kernel == LBM_KERNEL_TWO_ROW && (!is_single(h) || h->dims[1] % 2 != 0))
+                best.kernel = LBM_KERNEL_SCALAR;
+            return apply_choice(h, best);
         }
-    }
-    float best_ms = 0.f;
-    for (size_t k = 0; k < cand.size(); ++k)
-        if (k == 0 || cand_ms[k] < best_ms) {
-            best_ms = cand_ms[k];
-            best = cand[k];
+        HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+
+        std::vector<LaunchChoice> cand;
+        if (is_single(h)) {
+            for (int b : {64, 128, 256}) cand.push_back({LBM_KERNEL_SCALAR, b, 0});
+            cand.push_back({LBM_KERNEL_IN_PLACE, 256, 0});
+            if (h->dims[1] % 2 == 0) cand.push_back({LBM_KERNEL_TWO_ROW, 256, 0});
+            if (row_wave_sites(h)) cand.push_back({LBM_KERNEL_ROW_WAVE, 0, 0});
+        } else {
+            for (int b : {64, 128, 256})
+                for (int g : {0, 1024, 2048, 4096}) cand.push_back({LBM_KERNEL_SCALAR, b, g});
         }
-    // restore the state whatever happened
-    hipError_t re = hipMemcpyAsync(h->buf[cur0], saved, h->state_bytes, hipMemcpyDeviceToDevice, h->stream);
-    if (re == hipSuccess) re = hipStreamSynchronize(h->stream);
-    (void)hipFree(saved);
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-    h->cur = cur0;
-    h->t = t0;
-    if (st != LBM_OK) {
-        (void)apply_choice(h, old);
-        return st;
+
+        // tuning steps the state: keep a copy and restore it afterwards; the
+        // candidates switch kernels, so start from the natural layout in buf[0]
+        if (lbm_status st = canonicalize(h)) return st;
+        const int cur0 = h->cur;
+        const int64_t t0 = h->t;
+        const LaunchChoice old = {h->kernel, h->block, h->grid};
+        void* saved = nullptr;
+        HIP_TRY(hipMalloc(&saved, h->state_bytes), "hipMalloc(tuning copy)");
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        hipError_t e = hipMemcpyAsync(saved, h->buf[cur0], h->state_bytes, hipMemcpyDeviceToDevice, h->stream);
+        if (e == hipSuccess) e = hipEventCreate(&e0);
+        if (e == hipSuccess) e = hipEventCreate(&e1);
+        lbm_status st = (e == hipSuccess) ? LBM_OK : fail_hip(e, "tuning set-up");
+        // Every candidate is timed in kTuneRounds interleaved rounds and keeps its
+        // fastest round, so a slow window of the device (clock ramp, a neighbour's
+        // traffic) does not decide the choice.
+        std::vector<float> cand_ms(cand.size(), 0.f);
+        for (int round = 0; round < kTuneRounds && st == LBM_OK; ++round) {
+            for (size_t k = 0; k < cand.size() && st == LBM_OK; ++k) {
+                if ((st = apply_choice(h, cand[k])) != LBM_OK) break;
+                if ((st = lbm_step(h, 2)) != LBM_OK) break;
+                if ((e = hipEventRecord(e0, h->stream)) != hipSuccess) { st = fail_hip(e, "hipEventRecord"); break; }
+                if ((st = lbm_step(h, steps)) != LBM_OK) break;
+                if ((e = hipEventRecord(e1, h->stream)) != hipSuccess) { st = fail_hip(e, "hipEventRecord"); break; }
+                if ((e = hipEventSynchronize(e1)) != hipSuccess) { st = fail_hip(e, "hipEventSynchronize"); break; }
+                float ms = 0.f;
+                if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) { st = fail_hip(e, "hipEventElapsedTime"); break; }
+                if (round == 0 || ms < cand_ms[k]) cand_ms[k] = ms;
+            }
+        }
+        float best_ms = 0.f;
+        for (size_t k = 0; k < cand.size(); ++k)
+            if (k == 0 || cand_ms[k] < best_ms) {
+                best_ms = cand_ms[k];
+                best = cand[k];
+            }
+        // restore the state whatever happened
+        hipError_t re = hipMemcpyAsync(h->buf[cur0], saved, h->state_bytes, hipMemcpyDeviceToDevice, h->stream);
+        if (re == hipSuccess) re = hipStreamSynchronize(h->stream);
+        (void)hipFree(saved);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        h->cur = cur0;
+        h->t = t0;
+        if (st != LBM_OK) {
+            (void)apply_choice(h, old);
+            return st;
+        }
+        if (re != hipSuccess) return fail_hip(re, "restoring the state after tuning");
+        if (lbm_status ast = apply_choice(h, best)) return ast;
+        cache_store(cache_path, key, best);
+        return LBM_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(LBM_ENOMEM, "lbm_tune: host memory allocation failed");
+    } catch (...) {
+        return fail(LBM_EDEVICE, "lbm_tune: unexpected host exception");
     }
-    if (re != hipSuccess) return fail_hip(re, "restoring the state after tuning");
-    if (lbm_status ast = apply_choice(h, best)) return ast;
-    cache_store(cache_path, key, best);
-    return LBM_OK;
 }
 
 lbm_status lbm_moments(lbm_t h, double* rho, double* u, int32_t on_device)
 {
-    if (lbm_status st = check_handle(h)) return st;
-    if (!rho || !u) return fail(LBM_EINVAL, "rho or u is NULL");
-    if (!h->initialized) return fail(LBM_ESTATE, "lbm_moments before lbm_init");
-    HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
-    const size_t n = size_t(h->nsites);
-    const int D = h->lat.D;
-    double *drho = rho, *du = u;
-    if (!on_device) {
-        HIP_TRY(hipMalloc(&drho, n * (1 + D) * sizeof(double)), "hipMalloc(moments)");
-        du = drho + n;
+    try {
+        if (lbm_status st = check_handle(h)) return st;
+        if (!rho || !u) return fail(LBM_EINVAL, "rho or u is NULL");
+        if (!h->initialized) return fail(LBM_ESTATE, "lbm_moments before lbm_init");
+        HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+        const size_t n = size_t(h->nsites);
+        const int D = h->lat.D;
+        double *drho = rho, *du = u;
+        if (!on_device) {
+            HIP_TRY(hipMalloc(&drho, n * (1 + D) * sizeof(double)), "hipMalloc(moments)");
+            du = drho + n;
+        }
+        const void* state = nullptr;
+        bool swapped = false;
+        state_view(h, &state, &swapped);
+        hipError_t e = launch_moments(h->lattice, h->dtype, state, swapped, drho, du, h->d_chunks, h->nchunks,
+                                      h->d_boxes, h->nsites, h->stream);
+        if (e == hipSuccess && !on_device) {
+            e = hipMemcpyAsync(rho, drho, n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(u, du, n * D * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+        }
+        hipError_t e2 = hipStreamSynchronize(h->stream);
+        if (!on_device) (void)hipFree(drho);
+        if (e != hipSuccess) return fail_hip(e, "moments");
+        if (e2 != hipSuccess) return fail_hip(e2, "moments synchronize");
+        return LBM_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(LBM_ENOMEM, "lbm_moments: host memory allocation failed");
+    } catch (...) {
+        return fail(LBM_EDEVICE, "lbm_moments: unexpected host exception");
     }
-    const void* state = nullptr;
-    bool swapped = false;
-    state_view(h, &state, &swapped);
-    hipError_t e = launch_moments(h->lattice, h->dtype, state, swapped, drho, du, h->d_chunks, h->nchunks,
-                                  h->d_boxes, h->nsites, h->stream);
-    if (e == hipSuccess && !on_device) {
-        e = hipMemcpyAsync(rho, drho, n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(u, du, n * D * sizeof(double), hipMemcpyDeviceToHost, h->stream);
-    }
-    hipError_t e2 = hipStreamSynchronize(h->stream);
-    if (!on_device) (void)hipFree(drho);
-    if (e != hipSuccess) return fail_hip(e, "moments");
-    if (e2 != hipSuccess) return fail_hip(e2, "moments synchronize");
-    return LBM_OK;
 }
 
 lbm_status lbm_totals(lbm_t h, double* out)
 {
-    if (lbm_status st = check_handle(h)) return st;
-    if (!out) return fail(LBM_EINVAL, "out is NULL");
-    if (!h->initialized) return fail(LBM_ESTATE, "lbm_totals before lbm_init");
-    HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
-    const void* state = nullptr;
-    bool swapped = false;
-    state_view(h, &state, &swapped);
-    hipError_t e = launch_totals(h->lattice, h->dtype, state, swapped, h->d_chunks, h->nchunks,
-                                 h->d_box_chunk_begin, h->nbox, h->d_boxes, h->d_partial, h->d_out, h->stream);
-    if (e != hipSuccess) return fail_hip(e, "totals kernels");
-    HIP_TRY(hipMemcpyAsync(out, h->d_out, size_t(h->nbox) * 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream),
-            "copy totals");
-    HIP_TRY(hipStreamSynchronize(h->stream), "totals synchronize");
-    for (int b = 0; b < h->nbox; ++b) {
-        bool ok = out[4 * b] > 0.0;
-        for (int k = 0; k < 4; ++k) ok = ok && std::isfinite(out[4 * b + k]);
-        if (!ok) return fail(LBM_ENUMERIC, "box %d: non-finite totals or non-positive mass", b);
+    try {
+        if (lbm_status st = check_handle(h)) return st;
+        if (!out) return fail(LBM_EINVAL, "out is NULL");
+        if (!h->initialized) return fail(LBM_ESTATE, "lbm_totals before lbm_init");
+        HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+        const void* state = nullptr;
+        bool swapped = false;
+        state_view(h, &state, &swapped);
+        hipError_t e = launch_totals(h->lattice, h->dtype, state, swapped, h->d_chunks, h->nchunks,
+                                     h->d_box_chunk_begin, h->nbox, h->d_boxes, h->d_partial, h->d_out, h->stream);
+        if (e != hipSuccess) return fail_hip(e, "totals kernels");
+        HIP_TRY(hipMemcpyAsync(out, h->d_out, size_t(h->nbox) * 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream),
+                "copy totals");
+        HIP_TRY(hipStreamSynchronize(h->stream), "totals synchronize");
+        for (int b = 0; b < h->nbox; ++b) {
+            bool ok = out[4 * b] > 0.0;
+            for (int k = 0; k < 4; ++k) ok = ok && std::isfinite(out[4 * b + k]);
+            if (!ok) return fail(LBM_ENUMERIC, "box %d: non-finite totals or non-positive mass", b);
+        }
+        return LBM_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(LBM_ENOMEM, "lbm_totals: host memory allocation failed");
+    } catch (...) {
+        return fail(LBM_EDEVICE, "lbm_totals: unexpected host exception");
     }
-    return LBM_OK;
 }
 
 lbm_status lbm_residual(lbm_t h, const double* rho_ref, const double* u_ref, int32_t on_device, double out[4])
 {
-    if (lbm_status st = check_handle(h)) return st;
-    if (!rho_ref || !u_ref || !out) return fail(LBM_EINVAL, "NULL argument");
-    if (!h->initialized) return fail(LBM_ESTATE, "lbm_residual before lbm_init");
-    HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
-    const size_t n = size_t(h->nsites);
-    double *dr = nullptr, *du = nullptr;
-    bool t1 = false, t2 = false;
-    if (lbm_status st = stage_in(rho_ref, n, on_device, h->stream, &dr, &t1)) return st;
-    if (lbm_status st = stage_in(u_ref, n * h->lat.D, on_device, h->stream, &du, &t2)) {
+    try {
+        if (lbm_status st = check_handle(h)) return st;
+        if (!rho_ref || !u_ref || !out) return fail(LBM_EINVAL, "NULL argument");
+        if (!h->initialized) return fail(LBM_ESTATE, "lbm_residual before lbm_init");
+        HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+        const size_t n = size_t(h->nsites);
+        double *dr = nullptr, *du = nullptr;
+        bool t1 = false, t2 = false;
+        if (lbm_status st = stage_in(rho_ref, n, on_device, h->stream, &dr, &t1)) return st;
+        if (lbm_status st = stage_in(u_ref, n * h->lat.D, on_device, h->stream, &du, &t2)) {
+            if (t1) (void)hipFree(dr);
+            return st;
+        }
+        const void* state = nullptr;
+        bool swapped = false;
+        state_view(h, &state, &swapped);
+        hipError_t e = launch_residual(h->lattice, h->dtype, state, swapped, dr, du, h->d_chunks, h->nchunks,
+                                       h->d_boxes, h->nsites, h->d_partial, h->d_out, h->stream);
+        double tmp[4] = {0, 0, 0, 0};
+        if (e == hipSuccess) e = hipMemcpyAsync(tmp, h->d_out, 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+        hipError_t e2 = hipStreamSynchronize(h->stream);
         if (t1) (void)hipFree(dr);
-        return st;
+        if (t2) (void)hipFree(du);
+        if (e != hipSuccess) return fail_hip(e, "residual kernels");
+        if (e2 != hipSuccess) return fail_hip(e2, "residual synchronize");
+        out[0] = tmp[0];
+        out[1] = std::sqrt(tmp[1]);
+        out[2] = tmp[2];
+        out[3] = std::sqrt(tmp[3]);
+        return LBM_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(LBM_ENOMEM, "lbm_residual: host memory allocation failed");
+    } catch (...) {
+        return fail(LBM_EDEVICE, "lbm_residual: unexpected host exception");
     }
-    const void* state = nullptr;
-    bool swapped = false;
-    state_view(h, &state, &swapped);
-    hipError_t e = launch_residual(h->lattice, h->dtype, state, swapped, dr, du, h->d_chunks, h->nchunks,
-                                   h->d_boxes, h->nsites, h->d_partial, h->d_out, h->stream);
-    double tmp[4] = {0, 0, 0, 0};
-    if (e == hipSuccess) e = hipMemcpyAsync(tmp, h->d_out, 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream);
-    hipError_t e2 = hipStreamSynchronize(h->stream);
-    if (t1) (void)hipFree(dr);
-    if (t2) (void)hipFree(du);
-    if (e != hipSuccess) return fail_hip(e, "residual kernels");
-    if (e2 != hipSuccess) return fail_hip(e2, "residual synchronize");
-    out[0] = tmp[0];
-    out[1] = std::sqrt(tmp[1]);
-    out[2] = tmp[2];
-    out[3] = std::sqrt(tmp[3]);
-    return LBM_OK;
 }
 
 lbm_status lbm_checkpoint_bytes(lbm_t h, size_t* bytes)
 {
-    if (lbm_status st = check_handle(h)) return st;
-    if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
-    *bytes = sizeof(CkptHeader) + size_t(h->lat.Q) * size_t(h->nstored) * h->elem;
-    return LBM_OK;
+    try {
+        if (lbm_status st = check_handle(h)) return st;
+        if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
+        *bytes = sizeof(CkptHeader) + size_t(h->lat.Q) * size_t(h->nstored) * h->elem;
+        return LBM_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(LBM_ENOMEM, "lbm_checkpoint_bytes: host memory allocation failed");
+    } catch (...) {
+        return fail(LBM_EDEVICE, "lbm_checkpoint_bytes: unexpected host exception");
+    }
 }
 
 lbm_status lbm_get_state(lbm_t h, void* buf, size_t bytes)
 {
-    if (lbm_status st = check_handle(h)) return st;
-    size_t need = 0;
-    lbm_checkpoint_bytes(h, &need);
-    if (!buf || bytes < need) return fail(LBM_EINVAL, "checkpoint buffer needs %zu bytes", need);
-    if (!h->initialized) return fail(LBM_ESTATE, "lbm_get_state before lbm_init");
-    HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
-    CkptHeader hd;
-    std::memset(&hd, 0, sizeof(hd));
-    hd.magic = kCkptMagic;
-    hd.lattice = h->lattice;
-    hd.dtype = h->dtype;
-    hd.K = h->K;
-    hd.nbox = h->nbox;
-    hd.nsites = h->nsites;
-    hd.t = h->t;
-    hd.geometry_hash = geometry_hash(h);
-    hd.payload_bytes = need - sizeof(CkptHeader);
-    std::memcpy(buf, &hd, sizeof(hd));
-    char* dst = static_cast<char*>(buf) + sizeof(hd);
-    const void* state = nullptr;
-    bool swapped = false;
-    state_view(h, &state, &swapped);
-    const size_t payload = size_t(h->lat.Q) * size_t(h->nstored) * h->elem;
-    if (!swapped) {
-        HIP_TRY(hipMemcpyAsync(dst, state, payload, hipMemcpyDeviceToHost, h->stream), "copy state to host");
-        HIP_TRY(hipStreamSynchronize(h->stream), "get_state synchronize");
-    } else {
-        // the in-place step left the state swapped: copy it out as it is and
-        // put it into the natural layout on the host (no second device buffer)
-        std::vector<char> tmp;
-        try {
-            tmp.resize(payload);
-        } catch (const std::bad_alloc&) {
-            return fail(LBM_ENOMEM, "host staging for the checkpoint");
+    try {
+        if (lbm_status st = check_handle(h)) return st;
+        size_t need = 0;
+        lbm_checkpoint_bytes(h, &need);
+        if (!buf || bytes < need) return fail(LBM_EINVAL, "checkpoint buffer needs %zu bytes", need);
+        if (!h->initialized) return fail(LBM_ESTATE, "lbm_get_state before lbm_init");
+        HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+        CkptHeader hd;
+        std::memset(&hd, 0, sizeof(hd));
+        hd.magic = kCkptMagic;
+        hd.lattice = h->lattice;
+        hd.dtype = h->dtype;
+        hd.K = h->K;
+        hd.nbox = h->nbox;
+        hd.nsites = h->nsites;
+        hd.t = h->t;
+        hd.geometry_hash = geometry_hash(h);
+        hd.payload_bytes = need - sizeof(CkptHeader);
+        std::memcpy(buf, &hd, sizeof(hd));
+        char* dst = static_cast<char*>(buf) + sizeof(hd);
+        const void* state = nullptr;
+        bool swapped = false;
+        state_view(h, &state, &swapped);
+        const size_t payload = size_t(h->lat.Q) * size_t(h->nstored) * h->elem;
+        if (!swapped) {
+            HIP_TRY(hipMemcpyAsync(dst, state, payload, hipMemcpyDeviceToHost, h->stream), "copy state to host");
+            HIP_TRY(hipStreamSynchronize(h->stream), "get_state synchronize");
+        } else {
+            // the in-place step left the state swapped: copy it out as it is and
+            // put it into the natural layout on the host (no second device buffer)
+            std::vector<char> tmp;
+            try {
+                tmp.resize(payload);
+            } catch (const std::bad_alloc&) {
+                return fail(LBM_ENOMEM, "host staging for the checkpoint");
+            }
+            HIP_TRY(hipMemcpyAsync(tmp.data(), state, payload, hipMemcpyDeviceToHost, h->stream), "copy state to host");
+            HIP_TRY(hipStreamSynchronize(h->stream), "get_state synchronize");
+            unswap_host(h, tmp.data(), dst);
         }
-        HIP_TRY(hipMemcpyAsync(tmp.data(), state, payload, hipMemcpyDeviceToHost, h->stream), "copy state to host");
-        HIP_TRY(hipStreamSynchronize(h->stream), "get_state synchronize");
-        unswap_host(h, tmp.data(), dst);
+        return LBM_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(LBM_ENOMEM, "lbm_get_state: host memory allocation failed");
+    } catch (...) {
+        return fail(LBM_EDEVICE, "lbm_get_state: unexpected host exception");
     }
-    return LBM_OK;
 }
 
 lbm_status lbm_set_state(lbm_t h, const void* buf, size_t bytes)
 {
-    if (lbm_status st = check_handle(h)) return st;
-    size_t need = 0;
-    lbm_checkpoint_bytes(h, &need);
-    if (!buf || bytes < need) return fail(LBM_EINVAL, "checkpoint buffer needs %zu bytes", need);
-    CkptHeader hd;
-    std::memcpy(&hd, buf, sizeof(hd));
-    if (hd.magic != kCkptMagic) return fail(LBM_EINVAL, "not a checkpoint written by lbm_get_state");
-    if (hd.lattice != h->lattice || hd.dtype != h->dtype || hd.K != h->K || hd.nbox != h->nbox ||
-        hd.nsites != h->nsites || hd.geometry_hash != geometry_hash(h) || hd.payload_bytes != need - sizeof(hd))
-        return fail(LBM_EINVAL, "checkpoint does not match this handle (lattice, dtype, K or geometry)");
-    HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
-    if (lbm_status st = ensure_buffers(h)) return st;
-    if (lbm_status st = build_tiles(h)) return st;
-    const char* src = static_cast<const char*>(buf) + sizeof(hd);
-    if (lbm_status st = clear_padding(h)) return st;
-    HIP_TRY(hipMemcpyAsync(h->buf[0], src, size_t(h->lat.Q) * size_t(h->nstored) * h->elem, hipMemcpyHostToDevice,
-                           h->stream),
-            "copy state to device");
-    HIP_TRY(hipStreamSynchronize(h->stream), "set_state synchronize");
-    h->cur = 0;
-    h->t = hd.t;
-    h->initialized = true;
-    return LBM_OK;
+    try {
+        if (lbm_status st = check_handle(h)) return st;
+        size_t need = 0;
+        lbm_checkpoint_bytes(h, &need);
+        if (!buf || bytes < need) return fail(LBM_EINVAL, "checkpoint buffer needs %zu bytes", need);
+        CkptHeader hd;
+        std::memcpy(&hd, buf, sizeof(hd));
+        if (hd.magic != kCkptMagic) return fail(LBM_EINVAL, "not a checkpoint written by lbm_get_state");
+        if (hd.lattice != h->lattice || hd.dtype != h->dtype || hd.K != h->K || hd.nbox != h->nbox ||
+            hd.nsites != h->nsites || hd.geometry_hash != geometry_hash(h) || hd.payload_bytes != need - sizeof(hd))
+            return fail(LBM_EINVAL, "checkpoint does not match this handle (lattice, dtype, K or geometry)");
+        HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+        if (lbm_status st = ensure_buffers(h)) return st;
+        if (lbm_status st = build_tiles(h)) return st;
+        const char* src = static_cast<const char*>(buf) + sizeof(hd);
+        if (lbm_status st = clear_padding(h)) return st;
+        HIP_TRY(hipMemcpyAsync(h->buf[0], src, size_t(h->lat.Q) * size_t(h->nstored) * h->elem, hipMemcpyHostToDevice,
+                               h->stream),
+                "copy state to device");
+        HIP_TRY(hipStreamSynchronize(h->stream), "set_state synchronize");
+        h->cur = 0;
+        h->t = hd.t;
+        h->initialized = true;
+        return LBM_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(LBM_ENOMEM, "lbm_set_state: host memory allocation failed");
+    } catch (...) {
+        return fail(LBM_EDEVICE, "lbm_set_state: unexpected host exception");
+    }
 }
 
 lbm_status lbm_get_info(lbm_t h, lbm_info* info)
 {
-    if (lbm_status st = check_handle(h)) return st;
-    if (!info) return fail(LBM_EINVAL, "info is NULL");
-    std::memset(info, 0, sizeof(*info));
-    info->lattice = h->lattice;
-    info->dtype = h->dtype;
-    info->D = h->lat.D;
-    info->Q = h->lat.Q;
-    info->two_n = h->lat.two_n;
-    info->K = h->K;
-    info->T0 = h->lat.T0;
-    info->nbox = h->nbox;
-    for (int a = 0; a < 3; ++a) info->dims[a] = h->dims[a];
-    info->nsites = h->nsites;
-    info->t = h->t;
-    info->bytes_per_site_update = int64_t(2 * h->lat.Q) * int64_t(h->elem);
-    info->state_bytes = h->state_bytes;
-    info->block = effective_block(h);
-    info->grid = h->grid;
-    info->graph_chunk = h->graph_chunk;
-    info->kernel = effective_kernel(h);
-    info->collision = h->collision;
-    info->theta = h->theta;
-    return LBM_OK;
+    try {
+        if (lbm_status st = check_handle(h)) return st;
+        if (!info) return fail(LBM_EINVAL, "info is NULL");
+        std::memset(info, 0, sizeof(*info));
+        info->lattice = h->lattice;
+        info->dtype = h->dtype;
+        info->D = h->lat.D;
+        info->Q = h->lat.Q;
+        info->two_n = h->lat.two_n;
+        info->K = h->K;
+        info->T0 = h->lat.T0;
+        info->nbox = h->nbox;
+        for (int a = 0; a < 3; ++a) info->dims[a] = h->dims[a];
+        info->nsites = h->nsites;
+        info->t = h->t;
+        info->bytes_per_site_update = int64_t(2 * h->lat.Q) * int64_t(h->elem);
+        info->state_bytes = h->state_bytes;
+        info->block = effective_block(h);
+        info->grid = h->grid;
+        info->graph_chunk = h->graph_chunk;
+        info->kernel = effective_kernel(h);
+        info->collision = h->collision;
+        info->theta = h->theta;
+        return LBM_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(LBM_ENOMEM, "lbm_get_info: host memory allocation failed");
+    } catch (...) {
+        return fail(LBM_EDEVICE, "lbm_get_info: unexpected host exception");
+    }
 }
 
 lbm_status lbm_sync(lbm_t h)
 {
-    if (lbm_status st = check_handle(h)) return st;
-    HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
-    return LBM_OK;
+    try {
+        if (lbm_status st = check_handle(h)) return st;
+        HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+        return LBM_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(LBM_ENOMEM, "lbm_sync: host memory allocation failed");
+    } catch (...) {
+        return fail(LBM_EDEVICE, "lbm_sync: unexpected host exception");
+    }
 }
 
 lbm_status lbm_destroy(lbm_t h)
 {
-    if (!h) return LBM_OK;
-    (void)hipSetDevice(h->device);
-    (void)hipStreamSynchronize(h->stream);
-    free_all(h);
-    delete h;
-    return LBM_OK;
+    try {
+        if (!h) return LBM_OK;
+        (void)hipSetDevice(h->device);
+        (void)hipStreamSynchronize(h->stream);
+        free_all(h);
+        delete h;
+        return LBM_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(LBM_ENOMEM, "lbm_destroy: host memory allocation failed");
+    } catch (...) {
+        return fail(LBM_EDEVICE, "lbm_destroy: unexpected host exception");
+    }
 }
 
 const char* lbm_last_error(void) { return g_err.c_str(); }
@@ -1108,47 +1254,59 @@ const char* lbm_last_error(void) { return g_err.c_str(); }
 lbm_status lbm_lattice_table(int32_t lattice, int32_t* D, int32_t* Q, double* T0, int32_t* two_n, int32_t* c,
                              double* w)
 {
-    LatticeInfo L;
-    if (!lattice_info(lattice, &L)) return fail(LBM_EINVAL, "unknown lattice %d", lattice);
-    if (D) *D = L.D;
-    if (Q) *Q = L.Q;
-    if (T0) *T0 = L.T0;
-    if (two_n) *two_n = L.two_n;
-    for (int i = 0; i < L.Q; ++i) {
-        if (c)
-            for (int a = 0; a < 3; ++a) c[i * 3 + a] = L.c[i * 3 + a];
-        if (w) w[i] = L.w[i];
+    try {
+        LatticeInfo L;
+        if (!lattice_info(lattice, &L)) return fail(LBM_EINVAL, "unknown lattice %d", lattice);
+        if (D) *D = L.D;
+        if (Q) *Q = L.Q;
+        if (T0) *T0 = L.T0;
+        if (two_n) *two_n = L.two_n;
+        for (int i = 0; i < L.Q; ++i) {
+            if (c)
+                for (int a = 0; a < 3; ++a) c[i * 3 + a] = L.c[i * 3 + a];
+            if (w) w[i] = L.w[i];
+        }
+        return LBM_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(LBM_ENOMEM, "lbm_lattice_table: host memory allocation failed");
+    } catch (...) {
+        return fail(LBM_EDEVICE, "lbm_lattice_table: unexpected host exception");
     }
-    return LBM_OK;
 }
 
 lbm_status lbm_copy_probe(void* dst, const void* src, size_t bytes, int32_t reps, void* hip_stream,
                           double* ms_per_copy)
 {
-    if (!dst || !src || !ms_per_copy || reps < 1 || bytes == 0 || (bytes % 16) != 0)
-        return fail(LBM_EINVAL, "copy probe needs non-NULL buffers, reps >= 1 and bytes a positive multiple of 16");
-    int dev = 0;
-    if (lbm_status st = device_check(&dev)) return st;
-    hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
-    hipError_t e = hipEventCreate(&e1);
-    if (e != hipSuccess) {
+    try {
+        if (!dst || !src || !ms_per_copy || reps < 1 || bytes == 0 || (bytes % 16) != 0)
+            return fail(LBM_EINVAL, "copy probe needs non-NULL buffers, reps >= 1 and bytes a positive multiple of 16");
+        int dev = 0;
+        if (lbm_status st = device_check(&dev)) return st;
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        hipEvent_t e0, e1;
+        HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+        hipError_t e = hipEventCreate(&e1);
+        if (e != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            return fail_hip(e, "hipEventCreate");
+        }
+        e = launch_copy(dst, src, bytes, s);  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_copy(dst, src, bytes, s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
         (void)hipEventDestroy(e0);
-        return fail_hip(e, "hipEventCreate");
+        (void)hipEventDestroy(e1);
+        if (e != hipSuccess) return fail_hip(e, "copy probe");
+        *ms_per_copy = double(ms) / reps;
+        return LBM_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(LBM_ENOMEM, "lbm_copy_probe: host memory allocation failed");
+    } catch (...) {
+        return fail(LBM_EDEVICE, "lbm_copy_probe: unexpected host exception");
     }
-    e = launch_copy(dst, src, bytes, s);  // warm-up
-    if (e == hipSuccess) e = hipEventRecord(e0, s);
-    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_copy(dst, src, bytes, s);
-    if (e == hipSuccess) e = hipEventRecord(e1, s);
-    if (e == hipSuccess) e = hipEventSynchronize(e1);
-    float ms = 0.f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (e != hipSuccess) return fail_hip(e, "copy probe");
-    *ms_per_copy = double(ms) / reps;
-    return LBM_OK;
 }
 
 }  // extern "C"
