@@ -31,6 +31,8 @@ def traffic_file(kernel: str, workload: str = "turbulence256") -> str:
     headline box or on the 256-box batch."""
     if workload == "batch256":
         return os.path.join(ROOT, "profiles", "traffic_batch256_fp32.json")
+    if workload == "d3q39_192":
+        return os.path.join(ROOT, "profiles", f"traffic_d3q39_192_fp32_{kernel}.json")
     return os.path.join(ROOT, "profiles", f"traffic_d3q19_256_fp32_{kernel}.json")
 # what decides the step kernel's machine code: its sources and the compiler flags
 def _kernel_sources() -> list:
@@ -220,9 +222,10 @@ def main():
     ap.add_argument("--kernel", choices=["tune", "scalar", "row_wave", "in_place", "two_row"], default="tune",
                     help="headline step kernel: autotuned (default) or pinned")
     ap.add_argument("--block", type=int, default=256, help="threads per block when --kernel is pinned")
-    ap.add_argument("--workload", choices=["turbulence256", "batch256"], default="turbulence256",
-                    help="turbulence256: the headline box (default); batch256: only the 256-box FP32 batch, "
-                         "with its own roofline (a profiling aid)")
+    ap.add_argument("--workload", choices=["turbulence256", "batch256", "d3q39_192"], default="turbulence256",
+                    help="turbulence256: the headline box (default); batch256: only the 256-box FP32 batch; "
+                         "d3q39_192: only the D3Q39 192^3 FP32 shear wave; the last two print their own roofline "
+                         "(profiling aids)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -238,6 +241,9 @@ def main():
     lbm.load_library()
     if args.workload == "batch256":
         batch_only(args)
+        return
+    if args.workload == "d3q39_192":
+        d3q39_only(args)
         return
     tau = 0.51
     log("generating the 256^3 turbulence field")
@@ -369,6 +375,39 @@ def batch_only(args):
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "256 D3Q19 boxes, sides 16..64, tau 0.52..1, |U| <= 0.1, Taylor-Green, "
                                    "FP32 storage, Hermite order 3, one launch per step", "nsites": nsites},
+            "roofline": roofline, "conservation": m["conservation"], "cpu_baseline": None,
+            "copy_probe": {"bytes_moved": 2 * copy_bytes, "GB_s": copy_gbs, "frac_of_peak": copy_gbs / PEAK_HBM_GBS},
+            "frac_of_copy": m["achieved_GBs"] / copy_gbs}
+    print(json.dumps(line), flush=True)
+
+
+def d3q39_only(args):
+    """--workload d3q39_192: time the D3Q39 192^3 FP32 step (K = 4) alone and
+    print one JSON line with its roofline."""
+    from paper_2002_02503_amd import inputs, lbm
+
+    srho, su = inputs.shear_wave((192, 192, 192), 0.01, (0.2, 0.0, 0.0))
+    log(f"D3Q39 192^3 FP32: {args.warmup} warm-up + {args.steps} timed steps")
+    if args.kernel == "tune":
+        m = measure_box("D3Q39", (192, 192, 192), 0.6, "fp32", srho, su, args.steps, args.warmup)
+    else:
+        pin = {"kernel": args.kernel, "block": args.block if args.kernel != "row_wave" else 0}
+        m = measure_box("D3Q39", (192, 192, 192), 0.6, "fp32", srho, su, args.steps, args.warmup, tune=False, **pin)
+    nsites = m["nsites"]
+    traffic, traffic_src = traffic_per_launch(m["kernel"], "d3q39_192")
+    roofline = {"bound": "hbm", "achieved": m["achieved_GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": m["achieved_GBs"] / PEAK_HBM_GBS, "traffic": traffic,
+                "algorithmic_bytes_per_launch": m["bytes_per_site_update"] * nsites,
+                "kernel": KERNEL_SYMBOLS[m["kernel"]] + "<D3Q39, float, K=4>",
+                "launch": {"kernel": m["kernel"], "block": m["block"]}, "traffic_source": traffic_src}
+    copy_bytes = m["bytes_per_site_update"] // 2 * nsites
+    copy_ms = lbm.copy_probe(copy_bytes, reps=10)
+    copy_gbs = 2 * copy_bytes / (copy_ms * 1e-3) / 1e9
+    line = {"metric": "MLUPS & % HBM roofline, D3Q39 192^3 FP32", "value": m["value"], "unit": "MLUPS",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": m["ms_per_step"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "D3Q39 192^3 periodic shear wave 0.01 on U = (0.2, 0, 0), tau = 0.6, "
+                                   "FP32 storage, Hermite order 4", "nsites": nsites},
             "roofline": roofline, "conservation": m["conservation"], "cpu_baseline": None,
             "copy_probe": {"bytes_moved": 2 * copy_bytes, "GB_s": copy_gbs, "frac_of_peak": copy_gbs / PEAK_HBM_GBS},
             "frac_of_copy": m["achieved_GBs"] / copy_gbs}

@@ -203,11 +203,12 @@ lbm_status lbm_set_kernel(lbm_t h, int32_t kernel);
 /* Autotune the step's launch: time every candidate over `steps` steps with HIP
  * events, in three interleaved rounds, and keep the candidate with the fastest
  * round.  Single box: the scalar step at 64/128/256 threads per block, the
- * in-place step and the two-row step (ny even) at 256, and the row-wave step
- * where it applies.  Batch: 64/128/256 threads per block, with one wave per
- * 64-site block of the layout or 1024/2048/4096 persistent blocks.  The state is saved before and restored
- * after, so t and the populations are unchanged (all candidates compute the
- * same bits).  Choices are appended to the text file `cache_path` (NULL: the
+ * in-place step and the two-row step (ny even) at 256, the scalar and in-place
+ * steps at one whole x-row per block when nx rounds up to 192 lanes, and the
+ * row-wave step where it applies.  Batch: 64/128/256 threads per block, with
+ * one wave per 64-site block of the layout or 1024/2048/4096 persistent
+ * blocks.  The state is saved before and restored after, so t and the
+ * populations are unchanged (all candidates compute the same bits).  Choices are appended to the text file `cache_path` (NULL: the
  * path in the environment variable LBM_TUNE_CACHE, or no cache); a later call
  * with the same lattice, dtype, K, collision kind and geometry reuses the
  * cached choice without timing.  Needs an initialised handle (LBM_ESTATE

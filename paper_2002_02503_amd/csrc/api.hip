@@ -921,6 +921,14 @@ lbm_status lbm_tune(lbm_t h, int32_t steps, const char* cache_path)
         if (is_single(h)) {
             for (int b : {64, 128, 256}) cand.push_back({LBM_KERNEL_SCALAR, b, 0});
             cand.push_back({LBM_KERNEL_IN_PLACE, 256, 0});
+            // a block of one whole x-row (nx rounded up to 64 lanes) when that
+            // is none of the above: the x-shifted lines then stay within one
+            // workgroup (one L2) instead of being fetched by neighbouring ones
+            const int64_t row = ((h->dims[0] + 63) / 64) * 64;
+            if (row < 256 && row != 64 && row != 128) {
+                cand.push_back({LBM_KERNEL_SCALAR, int(row), 0});
+                cand.push_back({LBM_KERNEL_IN_PLACE, int(row), 0});
+            }
             if (h->dims[1] % 2 == 0) cand.push_back({LBM_KERNEL_TWO_ROW, 256, 0});
             if (row_wave_sites(h)) cand.push_back({LBM_KERNEL_ROW_WAVE, 0, 0});
         } else {

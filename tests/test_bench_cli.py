@@ -19,7 +19,7 @@ def test_bench_help_lists_the_workloads():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"], cwd=ROOT,
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 0
-    assert "turbulence256" in r.stdout and "batch256" in r.stdout
+    assert "turbulence256" in r.stdout and "batch256" in r.stdout and "d3q39_192" in r.stdout
 
 
 def test_traffic_counters_apply_only_to_the_sources_they_were_taken_on(tmp_path, monkeypatch):

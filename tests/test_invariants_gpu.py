@@ -197,7 +197,7 @@ def test_batch_of_equal_boxes_equals_single_boxes():
 
 
 @pytest.mark.parametrize("lattice,dims,dtype", [("D3Q19", (64, 12, 10), "fp32"), ("D3Q19", (64, 12, 10), "bf16"),
-                                                ("D3Q39", (48, 9, 7), "fp32")])
+                                                ("D3Q39", (48, 9, 7), "fp32"), ("D3Q39", (150, 6, 4), "fp32")])
 def test_tuning_restores_state_and_keeps_results(lattice, dims, dtype, tmp_path):
     """lbm_tune times every candidate launch on the live state, restores it,
     and whatever it picks computes the same bits; its cache is reused."""
