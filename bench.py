@@ -26,14 +26,14 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS & % HBM roofline, D3Q19 256³ FP32 vs FP16-storage at stated error"
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E peak
-def traffic_file(kernel: str, workload: str = "turbulence256") -> str:
+def traffic_file(kernel: str, workload: str = "turbulence256", dtype: str = "fp32") -> str:
     """Committed counter summary of the step for one kernel variant, on the
-    headline box or on the 256-box batch."""
+    headline box (in one storage type), the 256-box batch or the D3Q39 box."""
     if workload == "batch256":
         return os.path.join(ROOT, "profiles", "traffic_batch256_fp32.json")
     if workload == "d3q39_192":
         return os.path.join(ROOT, "profiles", f"traffic_d3q39_192_fp32_{kernel}.json")
-    return os.path.join(ROOT, "profiles", f"traffic_d3q19_256_fp32_{kernel}.json")
+    return os.path.join(ROOT, "profiles", f"traffic_d3q19_256_{dtype}_{kernel}.json")
 # what decides the step kernel's machine code: its sources and the compiler flags
 def _kernel_sources() -> list:
     """Every source that goes into the device code (all of csrc/ except the
@@ -124,13 +124,13 @@ def pcie_inclusive(m) -> dict:
             "note": "lbm_init from host float64 rho, u + timed steps + lbm_moments to host"}
 
 
-def traffic_per_launch(kernel: str, workload: str = "turbulence256"):
+def traffic_per_launch(kernel: str, workload: str = "turbulence256", dtype: str = "fp32"):
     """HBM bytes per launch of the FP32 256^3 step of a kernel variant from the
     committed rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, scaled by the
     copy-kernel calibration), or None when absent or taken on other kernel
     sources.  For the in-place variant a launch is one of its two alternating
     forms, averaged over both."""
-    path = traffic_file(kernel, workload)
+    path = traffic_file(kernel, workload, dtype)
     if not os.path.exists(path):
         return None, "no counter summary"
     with open(path) as f:
@@ -222,6 +222,8 @@ def main():
     ap.add_argument("--kernel", choices=["tune", "scalar", "row_wave", "in_place", "two_row"], default="tune",
                     help="headline step kernel: autotuned (default) or pinned")
     ap.add_argument("--block", type=int, default=256, help="threads per block when --kernel is pinned")
+    ap.add_argument("--dtype", choices=["fp32", "fp16", "bf16"], default="fp32",
+                    help="storage type of the headline box (fp32 is the headline; the others are profiling aids)")
     ap.add_argument("--workload", choices=["turbulence256", "batch256", "d3q39_192"], default="turbulence256",
                     help="turbulence256: the headline box (default); batch256: only the 256-box FP32 batch; "
                          "d3q39_192: only the D3Q39 192^3 FP32 shear wave; the last two print their own roofline "
@@ -249,19 +251,21 @@ def main():
     log("generating the 256^3 turbulence field")
     rho, u = inputs.turbulence(256)
 
-    log(f"FP32 256^3: {args.warmup} warm-up + {args.steps} timed steps")
+    hd = args.dtype
+    log(f"{hd.upper()} 256^3: {args.warmup} warm-up + {args.steps} timed steps")
     if args.kernel == "tune":
-        head = measure_box("D3Q19", (256, 256, 256), tau, "fp32", rho, u, args.steps, args.warmup)
+        head = measure_box("D3Q19", (256, 256, 256), tau, hd, rho, u, args.steps, args.warmup)
     else:
         pin = {"kernel": args.kernel, "block": args.block if args.kernel != "row_wave" else 0}
-        head = measure_box("D3Q19", (256, 256, 256), tau, "fp32", rho, u, args.steps, args.warmup, tune=False, **pin)
+        head = measure_box("D3Q19", (256, 256, 256), tau, hd, rho, u, args.steps, args.warmup, tune=False, **pin)
     log(f"headline: {head['value']:.0f} MLUPS with the {head['kernel']} step, block {head['block']}")
     nsites = head["nsites"]
-    traffic, traffic_src = traffic_per_launch(head["kernel"])
+    traffic, traffic_src = traffic_per_launch(head["kernel"], "turbulence256", hd)
     roofline = {"bound": "hbm", "achieved": head["achieved_GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": head["achieved_GBs"] / PEAK_HBM_GBS, "traffic": traffic,
                 "algorithmic_bytes_per_launch": head["bytes_per_site_update"] * nsites,
-                "kernel": KERNEL_SYMBOLS[head["kernel"]] + "<D3Q19, float, K=3>",
+                "kernel": KERNEL_SYMBOLS[head["kernel"]] + "<D3Q19, "
+                          + {"fp32": "float", "fp16": "_Float16", "bf16": "bf16_t"}[hd] + ", K=3>",
                 "launch": {"kernel": head["kernel"], "block": head["block"]}, "traffic_source": traffic_src}
 
     log("copy probe at the same footprint")
@@ -320,7 +324,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "D3Q19 256^3 periodic, decaying turbulence (k0=4, u_rms=0.04, seeded), "
-                               "tau=0.51, FP32 storage of S(f_i - w_i), Hermite order 3",
+                               f"tau=0.51, {hd.upper()} storage of S(f_i - w_i), Hermite order 3",
                    "lattice": "D3Q19", "dims": [256, 256, 256], "tau": tau, "hermite_order": 3},
         "roofline": roofline,
         "conservation": head["conservation"],

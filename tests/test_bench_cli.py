@@ -31,13 +31,13 @@ def test_traffic_counters_apply_only_to_the_sources_they_were_taken_on(tmp_path,
 
     f = tmp_path / "traffic.json"
     json.dump({"source_hash": "abc", "traffic_bytes_per_launch": 123.0}, open(f, "w"))
-    monkeypatch.setattr(bench, "traffic_file", lambda kernel, workload="turbulence256": str(f))
+    monkeypatch.setattr(bench, "traffic_file", lambda kernel, workload="turbulence256", dtype="fp32": str(f))
     monkeypatch.setattr(bench, "source_hash", lambda: "abc")
     assert bench.traffic_per_launch("scalar")[0] == 123.0
     monkeypatch.setattr(bench, "source_hash", lambda: "def")
     value, why = bench.traffic_per_launch("scalar")
     assert value is None and "changed" in why
-    monkeypatch.setattr(bench, "traffic_file", lambda kernel, workload="turbulence256": str(tmp_path / "none.json"))
+    monkeypatch.setattr(bench, "traffic_file", lambda kernel, workload="turbulence256", dtype="fp32": str(tmp_path / "none.json"))
     assert bench.traffic_per_launch("scalar")[0] is None
 
 
