@@ -230,7 +230,7 @@ def main():
                          "(profiling aids)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the slab decomposition over xGMI is a design, not code). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
