@@ -215,3 +215,28 @@ def test_batch_box_limits():
         r0, u0 = _box_fields(dims, rho, u, k)
         r1, u1 = run_gpu("D3Q19", d, [0.6, 0.7][k], "fp32", r0, u0, 3)
         assert np.array_equal(rb[k], r1) and np.array_equal(ub[k], u1), d
+
+
+def test_size_limits_are_refused_before_allocation():
+    """The documented limits of lbm_create / lbm_create_batch, each refused
+    with LBM_EINVAL before any device memory is touched: 2^31 sites in total,
+    ny and nz at most 65535, and less than 2 GiB of populations per batch box
+    (the batched kernel's 32-bit offsets)."""
+    from paper_2002_02503_amd import lbm
+
+    cases = [
+        ("D3Q19", (2 ** 11, 2 ** 10, 2 ** 10), 0.6),  # 2^31 sites
+        ("D3Q19", (1, 65536, 1), 0.6),                 # ny > 65535
+        ("D3Q19", (1, 1, 65536), 0.6),                 # nz > 65535
+    ]
+    for lattice, dims, tau in cases:
+        with pytest.raises(lbm.LBMError) as e:
+            lbm.Simulation(lattice, dims, tau)
+        assert e.value.name == "LBM_EINVAL", dims
+    big = (1024, 1024, 14)  # 14.7 M sites * 19 * 8 B = 2.2 GiB in FP64
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.Simulation("D3Q19", [big, (8, 8, 8)], [0.6, 0.7], dtype="fp64")
+    assert e.value.name == "LBM_EINVAL" and "2 GiB" in str(e.value)
+    # the same box alone is a single box (64-bit row offsets): accepted, nothing allocated yet
+    with lbm.Simulation("D3Q19", big, 0.6, dtype="fp64", torch_memory=False) as sim:
+        assert sim.info()["nsites"] == 1024 * 1024 * 14
