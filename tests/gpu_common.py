@@ -40,9 +40,10 @@ def run_oracle(lattice, dims, tau, rho, u, steps, K=None, mode="literal", **kw):
     return sim.moments()
 
 
-def lightcone_samples(lattice, rho0, u0, tau, steps, points, K=None):
+def lightcone_samples(lattice, rho0, u0, tau, steps, points, K=None, mode="closed", **kw):
     """Oracle (rho, u) at `points` (list of (z, y, x)) after `steps` steps of a
-    run started from (rho0, u0) on the full periodic box."""
+    run started from (rho0, u0) on the full periodic box.  Further keywords
+    (kind, theta) go to the oracle's Sim."""
     L = oracle.lattice(lattice)
     D = L["D"]
     R = int(np.abs(L["c"]).max())
@@ -57,7 +58,7 @@ def lightcone_samples(lattice, rho0, u0, tau, steps, points, K=None):
         sub_r = rho0[np.ix_(iz, iy, ix)]
         sub_u = u0[(slice(None),) + np.ix_(iz, iy, ix)]
         dims = (side, side, side if D == 3 else 1)
-        sim = oracle.Sim(lattice, dims, tau, K=K, mode="closed").init(sub_r, sub_u).step(steps)
+        sim = oracle.Sim(lattice, dims, tau, K=K, mode=mode, **kw).init(sub_r, sub_u).step(steps)
         rr, uu = sim.moments()
         cz = r if D == 3 else 0
         rho_out.append(rr[cz, r, r])
