@@ -97,9 +97,12 @@ typedef struct {
 } lbm_info;
 
 /* Create a single periodic box (eq. lbe on an nx*ny*nz torus).
- * dims = {nx, ny, nz}, each >= 1; D2Q9 requires nz == 1.  nx and the total
- * number of sites must be below 2^31, ny and nz at most 65535; in a batch
- * every box holds less than 2 GiB of populations and has nx at most 2^21.
+ * dims = {nx, ny, nz}, each >= 1; D2Q9 requires nz == 1.  ny and nz at most
+ * 65535 with ny * nz below 2^31; one population row (nx times the storage
+ * bytes) below 2 GiB; at most 2^36 sites in total (memory is the practical
+ * limit: a D3Q19 FP16 box of 2^32 sites takes 163 GB with the in-place
+ * step); in a batch every box holds less than 2 GiB of populations and has nx
+ * at most 2^21.
  * tau: relaxation time, finite and > 1/2 (viscosity T0 (tau - 1/2)).  No
  * device memory for the populations is allocated until lbm_init /
  * lbm_set_state, unless bound with lbm_bind_state.  Errors: LBM_EINVAL,

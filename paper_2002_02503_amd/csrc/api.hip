@@ -54,6 +54,7 @@ lbm_status fail_hip(hipError_t e, const char* what)
 
 constexpr int kChunkSites = 4096;   // sites per reduction chunk
 constexpr int kBlockSites = 64;     // sites per block of a batched box's layout (one wave)
+constexpr int64_t kMaxSites = int64_t(1) << 36;  // total sites: keeps chunk and tile counts in int
 constexpr int kDefaultGraphChunk = 32;
 constexpr int kTuneRounds = 3;
 constexpr uint64_t kCkptMagic = 0x314b4350434d424cULL;  // "LBMCPCK1"
@@ -203,8 +204,8 @@ lbm_status validate_box(int lattice, const int64_t* d, double tau, const Lattice
         if (d[a] < 1 || d[a] > INT32_MAX)
             return fail(LBM_EINVAL, "box %d: dims[%d] = %lld outside [1, 2^31)", index, a, (long long)d[a]);
     }
-    if (d[0] * d[1] > INT32_MAX || d[0] * d[1] * d[2] > INT32_MAX)
-        return fail(LBM_EINVAL, "box %d: site count must be below 2^31", index);
+    // the step kernels index x-rows r = z ny + y in 32 bits
+    if (d[1] * d[2] > INT32_MAX) return fail(LBM_EINVAL, "box %d: ny * nz must be below 2^31", index);
     if (L.D == 2 && d[2] != 1) return fail(LBM_EINVAL, "box %d: a 2-D lattice needs nz == 1", index);
     if (!std::isfinite(tau) || !(tau > 0.5)) return fail(LBM_EINVAL, "box %d: tau must be finite and > 1/2", index);
     (void)lattice;
@@ -271,7 +272,10 @@ lbm_status create_common(lbm_t* out, int32_t lattice, int32_t nbox, const int64_
         lbm_status st = validate_box(lattice, dims + 3 * b, tau[b], L, b);
         if (st != LBM_OK) return st;
         total += dims[3 * b] * dims[3 * b + 1] * dims[3 * b + 2];
-        if (total > INT32_MAX) return fail(LBM_EINVAL, "total site count must be below 2^31");
+        if (total > kMaxSites) return fail(LBM_EINVAL, "total site count must be at most 2^36");
+        // lane offsets inside one population row are formed in 32 bits
+        if (dims[3 * b] * int64_t(storage_bytes(dtype)) > INT32_MAX)
+            return fail(LBM_EINVAL, "box %d: a population row (nx * storage bytes) must be below 2 GiB", b);
     }
     int dev = 0;
     lbm_status st = device_check(&dev);

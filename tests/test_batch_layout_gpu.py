@@ -219,24 +219,69 @@ def test_batch_box_limits():
 
 def test_size_limits_are_refused_before_allocation():
     """The documented limits of lbm_create / lbm_create_batch, each refused
-    with LBM_EINVAL before any device memory is touched: 2^31 sites in total,
-    ny and nz at most 65535, and less than 2 GiB of populations per batch box
-    (the batched kernel's 32-bit offsets)."""
+    with LBM_EINVAL before any device memory is touched: ny and nz at most
+    65535 with ny * nz below 2^31 (32-bit row indices), a population row
+    below 2 GiB (32-bit lane offsets), at most 2^36 sites, and less than 2 GiB
+    of populations per batch box (the batched kernel's 32-bit offsets)."""
     from paper_2002_02503_amd import lbm
 
     cases = [
-        ("D3Q19", (2 ** 11, 2 ** 10, 2 ** 10), 0.6),  # 2^31 sites
-        ("D3Q19", (1, 65536, 1), 0.6),                 # ny > 65535
-        ("D3Q19", (1, 1, 65536), 0.6),                 # nz > 65535
+        ("D3Q19", (1, 65536, 1), "fp32"),               # ny > 65535
+        ("D3Q19", (1, 1, 65536), "fp32"),               # nz > 65535
+        ("D3Q19", (1, 65535, 65535), "fp32"),           # ny * nz >= 2^31
+        ("D2Q9", (2 ** 28, 1, 1), "fp64"),              # 2 GiB population rows
+        ("D3Q19", (2 ** 20, 256, 65535), "fp16"),       # more than 2^36 sites
     ]
-    for lattice, dims, tau in cases:
+    for lattice, dims, dtype in cases:
         with pytest.raises(lbm.LBMError) as e:
-            lbm.Simulation(lattice, dims, tau)
+            lbm.Simulation(lattice, dims, 0.6, dtype=dtype, torch_memory=False)
         assert e.value.name == "LBM_EINVAL", dims
     big = (1024, 1024, 14)  # 14.7 M sites * 19 * 8 B = 2.2 GiB in FP64
     with pytest.raises(lbm.LBMError) as e:
         lbm.Simulation("D3Q19", [big, (8, 8, 8)], [0.6, 0.7], dtype="fp64")
     assert e.value.name == "LBM_EINVAL" and "2 GiB" in str(e.value)
-    # the same box alone is a single box (64-bit row offsets): accepted, nothing allocated yet
-    with lbm.Simulation("D3Q19", big, 0.6, dtype="fp64", torch_memory=False) as sim:
-        assert sim.info()["nsites"] == 1024 * 1024 * 14
+    # accepted, nothing allocated yet: the same box alone (64-bit row
+    # offsets), a 2^31-site box and a 2^28-site row in FP32
+    for dims, dtype in [(big, "fp64"), ((2 ** 11, 2 ** 10, 2 ** 10), "fp32"), ((2 ** 28, 1, 1), "fp32")]:
+        lattice = "D2Q9" if dims[1:] == (1, 1) else "D3Q19"
+        with lbm.Simulation(lattice, dims, 0.6, dtype=dtype, torch_memory=False) as sim:
+            assert sim.info()["nsites"] == dims[0] * dims[1] * dims[2]
+
+
+def test_box_of_more_than_2_31_sites():
+    """A single D3Q19 box of 2^31 + 2^20 sites (1024 x 1024 x 2049), FP16, in
+    place (82 GB of populations, fields on the device): a shear wave along x
+    stays x-only bit for bit and equals the 1024 x 1 x 1 box's run."""
+    import torch
+
+    from paper_2002_02503_amd import lbm
+
+    nx, ny, nz = 1024, 1024, 2049
+    U, tau, steps = (0.05, 0.02, -0.03), 0.6, 5
+    x = torch.arange(nx, dtype=torch.float64, device="cuda")
+    rho = torch.ones((nz, ny, nx), dtype=torch.float64, device="cuda")
+    u = torch.empty((3, nz, ny, nx), dtype=torch.float64, device="cuda")
+    u[0] = U[0]
+    u[1] = U[1] + 0.01 * torch.sin(2 * torch.pi * x / nx)
+    u[2] = U[2]
+    with lbm.Simulation("D3Q19", (nx, ny, nz), tau, dtype="fp16", kernel="in_place", torch_memory=False) as sim:
+        assert sim.info()["nsites"] > 2 ** 31
+        sim.init(rho, u)  # synchronises: the fields can go before the outputs are made
+        del rho, u, x
+        torch.cuda.empty_cache()
+        sim.step(steps)
+        r, uu = sim.moments(device=True)
+    assert torch.equal(uu, uu[:, :1, :1, :].expand_as(uu))
+    assert torch.equal(r, r[:1, :1, :].expand_as(r))
+    row_u, row_r = uu[:, 0, 0, :].cpu().numpy(), r[0, 0, :].cpu().numpy()
+    del r, uu
+    torch.cuda.empty_cache()
+    rho1 = np.ones((1, 1, nx))
+    u1 = np.empty((3, 1, 1, nx))
+    u1[0] = U[0]
+    u1[1] = U[1] + 0.01 * np.sin(2 * np.pi * np.arange(nx) / nx)
+    u1[2] = U[2]
+    with lbm.Simulation("D3Q19", (nx, 1, 1), tau, dtype="fp16", kernel="in_place") as one:
+        one.init(rho1, u1).step(steps)
+        r1, uu1 = one.moments()
+    assert np.array_equal(row_u, uu1[:, 0, 0, :]) and np.array_equal(row_r, r1[0, 0, :])
