@@ -913,6 +913,10 @@ lbm_status lbm_tune(lbm_t h, int32_t steps, const char* cache_path)
         const std::string key = tune_key(h);
         LaunchChoice best;
         if (cache_lookup(cache_path, key, &best)) {
+            // the cache is a text file: take only values this library can launch
+            if (best.kernel < LBM_KERNEL_AUTO || best.kernel > LBM_KERNEL_TWO_ROW) best.kernel = LBM_KERNEL_SCALAR;
+            if (!(best.block == 0 || (best.block >= 64 && best.block <= 256 && best.block % 64 == 0))) best.block = 0;
+            if (best.grid < 0) best.grid = 0;
             if (best.kernel == LBM_KERNEL_ROW_WAVE && !row_wave_sites(h)) best.kernel = LBM_KERNEL_SCALAR;
             if (best.kernel == LBM_KERNEL_IN_PLACE && !is_single(h)) best.kernel = LBM_KERNEL_SCALAR;
             if (best.kernel == LBM_KERNEL_TWO_ROW && (!is_single(h) || h->dims[1] % 2 != 0))

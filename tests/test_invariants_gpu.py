@@ -235,3 +235,26 @@ def test_tuning_a_batch_keeps_results(tmp_path):
         rb, ub = b.moments()
         assert b.info()["block"] in (64, 128, 256)
     assert np.array_equal(ra, rb) and np.array_equal(ua, ub)
+
+
+def test_tuning_cache_with_bad_entries(tmp_path):
+    """A cache line edited to values the library cannot launch (unknown kernel,
+    a block that is not a multiple of 64, a negative grid) is replaced by valid
+    ones, and the run still computes the reference bits."""
+    dims = (96, 6, 5)
+    rho, u = _fields(dims, 13)
+    ref = run_gpu("D3Q19", dims, 0.6, "fp32", rho, u, 12)
+    cache = tmp_path / "tune.txt"
+    with lbm.Simulation("D3Q19", dims, 0.6, dtype="fp32") as sim:
+        sim.init(rho, u).tune(steps=3, cache=str(cache))
+    key = open(cache).read().splitlines()[-1].split(" | ")[0]
+    with open(cache, "a") as f:
+        f.write(key + " | 99 96 -5\n")
+        f.write("garbage without a separator\n")
+    with lbm.Simulation("D3Q19", dims, 0.6, dtype="fp32") as sim:
+        sim.init(rho, u).tune(steps=3, cache=str(cache))
+        info = sim.info()
+        assert info["block"] in (64, 128, 192, 256) and info["grid"] >= 0
+        sim.step(12)
+        r, uu = sim.moments()
+    assert np.array_equal(r, ref[0]) and np.array_equal(uu, ref[1])
