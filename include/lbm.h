@@ -174,8 +174,8 @@ lbm_status lbm_step(lbm_t h, int64_t n);
  * does not pay for graph instantiation.  Optional. */
 lbm_status lbm_prepare(lbm_t h);
 
-/* Steps per captured graph (>= 1; default 32).  Takes effect at the next
- * lbm_step / lbm_prepare. */
+/* Steps per captured graph, 1 to 4096 (default 32; else LBM_EINVAL).  Takes
+ * effect at the next lbm_step / lbm_prepare. */
 lbm_status lbm_set_graph_chunk(lbm_t h, int32_t steps);
 
 /* Launch shape: threads per block (64, 128 or 256; 0 = default) and,
