@@ -278,6 +278,8 @@ def main():
         for dt in ["fp16", "bf16"]:
             log(f"{dt} storage 256^3")
             variants[dt] = measure_box("D3Q19", (256, 256, 256), tau, dt, rho, u, args.steps, args.warmup)
+        log("fp64 storage 256^3, 300 steps")
+        variants["fp64"] = measure_box("D3Q19", (256, 256, 256), tau, "fp64", rho, u, 300, args.warmup)
         log("batched: 256 D3Q19 boxes, 1000 steps")
         bdims, btaus, brho, bu = batch_fields()
         variants["batched_fp32"] = measure_box("D3Q19", bdims, btaus, "fp32", brho, bu, 1000, args.warmup)
