@@ -306,6 +306,15 @@ def main():
         log("D3Q15 on the 256^3 turbulence box, FP32, 300 steps")
         variants["d3q15_fp32_256"] = measure_box("D3Q15", (256, 256, 256), tau, "fp32", rho, u, 300, args.warmup)
 
+    # measured HBM traffic of the variants whose launch has a committed counter summary
+    for name, wl, dt in [("fp16", "turbulence256", "fp16"), ("bf16", "turbulence256", "bf16"),
+                         ("batched_fp32", "batch256", "fp32"), ("d3q39_fp32_192", "d3q39_192", "fp32")]:
+        if name in variants:
+            v = variants[name]
+            tb, src = traffic_per_launch(v["kernel"], wl, dt)
+            v["traffic_over_algorithmic"] = tb / (v["bytes_per_site_update"] * v["nsites"]) if tb else None
+            v["traffic_source"] = src
+
     cpu, errors = None, {}
     if not args.no_cpu_baseline:
         log("CPU baseline leg: FP64 oracle on the host cores, and the error statements")
