@@ -103,3 +103,37 @@ def test_higher_order_lattice_is_more_galilean(oracle_mod):
         err[name] = abs(gU / g0 - 1)
     assert err["D3Q39"] < err["D3Q19"] / 2
     assert err["D3Q39"] < 5e-5
+
+
+@pytest.mark.parametrize("K", [2, 3])
+def test_bgk_shear_wave_decay_at_rest(oracle_mod, K):
+    """eq. BGK with the equilibrium truncated at K: the same closed-form shear
+    viscosity nu = T0 (tau - 1/2) as the filtered operator (D3Q19 64, tau = 0.6,
+    2000 steps).  Pins the relaxation factor of the BGK branch itself: 1 - 1/tau
+    or tau in place of 1/tau gives another viscosity (or no decay at all)."""
+    O = oracle_mod
+    nx, tau = 64, 0.6
+    ts, amps = _shear_run(O, "D3Q19", nx, tau, (0.0, 0.0, 0.0), 2000, kind="bgk", K=K, Keq=K)
+    k = 2 * np.pi / nx
+    assert abs(fit_decay(ts, amps) / (_nu(O, "D3Q19", tau) * k * k) - 1) < 1e-3
+
+
+@pytest.mark.parametrize("K", [2, 3])
+def test_bgk_taylor_green_decay_d2q9(oracle_mod, K):
+    """eq. BGK on the D2Q9 Taylor-Green vortex (64 x 64, tau = 0.8, 1000 steps):
+    u decays as exp(-2 nu k^2 t) with nu = T0 (tau - 1/2)."""
+    O = oracle_mod
+    n, tau, u0 = 64, 0.8, 0.05
+    sim = O.Sim("D2Q9", (n, n, 1), tau, kind="bgk", K=K, Keq=K)
+    rho, u = inputs.taylor_green_2d(n, u0, O.lattice("D2Q9")["T0"])
+    sim.init(rho, u)
+    ts, amps = [], []
+    for t in range(0, 1001, 50):
+        if t:
+            sim.step(50)
+        _, uu = sim.moments()
+        ts.append(t)
+        amps.append(np.sqrt(np.mean(uu * uu)))
+    k = 2 * np.pi / n
+    g_th = 2 * _nu(O, "D2Q9", tau) * k * k
+    assert abs(fit_decay(ts, amps) / g_th - 1) < 1e-3
