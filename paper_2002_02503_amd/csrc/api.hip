@@ -267,15 +267,28 @@ lbm_status create_common(lbm_t* out, int32_t lattice, int32_t nbox, const int64_
     if (storage_bytes(dtype) == 0) return fail(LBM_EINVAL, "unknown dtype %d", dtype);
     if (nbox < 1) return fail(LBM_EINVAL, "nbox must be >= 1");
     if (!dims || !tau) return fail(LBM_EINVAL, "dims or tau is NULL");
+    // every argument is checked here, on the host, before any device call
     int64_t total = 0;
     for (int b = 0; b < nbox; ++b) {
         lbm_status st = validate_box(lattice, dims + 3 * b, tau[b], L, b);
         if (st != LBM_OK) return st;
-        total += dims[3 * b] * dims[3 * b + 1] * dims[3 * b + 2];
+        const int64_t nx = dims[3 * b], ny = dims[3 * b + 1], nz = dims[3 * b + 2];
+        total += nx * ny * nz;
         if (total > kMaxSites) return fail(LBM_EINVAL, "total site count must be at most 2^36");
         // lane offsets inside one population row are formed in 32 bits
-        if (dims[3 * b] * int64_t(storage_bytes(dtype)) > INT32_MAX)
+        if (nx * int64_t(storage_bytes(dtype)) > INT32_MAX)
             return fail(LBM_EINVAL, "box %d: a population row (nx * storage bytes) must be below 2 GiB", b);
+        // y and z are grid coordinates of the single-box kernels
+        if (ny > 65535 || nz > 65535) return fail(LBM_EINVAL, "box %d: ny and nz must be at most 65535", b);
+        if (nbox > 1) {
+            // a batch box is addressed with 32-bit element offsets
+            const uint64_t padded = (uint64_t(nx * ny * nz) + kBlockSites - 1) / kBlockSites * kBlockSites;
+            if (padded * uint64_t(L.Q) * storage_bytes(dtype) >= (uint64_t(1) << 31))
+                return fail(LBM_EINVAL, "box %d of a batch must hold less than 2 GiB of populations", b);
+            // the batched step splits a lane's site with a float reciprocal,
+            // exact while x0 + 64 stays below 2^22
+            if (nx > (int64_t(1) << 21)) return fail(LBM_EINVAL, "box %d of a batch: nx must be at most 2^21", b);
+        }
     }
     int dev = 0;
     lbm_status st = device_check(&dev);
@@ -313,27 +326,6 @@ lbm_status create_common(lbm_t* out, int32_t lattice, int32_t nbox, const int64_
         h->elem = storage_bytes(dtype);
         // Q * nstored elements, allocation rounded to 256 bytes
         h->state_bytes = ((size_t(h->nstored) * size_t(L.Q) * h->elem + 255) / 256) * 256;
-        if (nbox > 1)
-            for (int b = 0; b < nbox; ++b) {
-                const uint64_t nb = uint64_t(dims[3 * b]) * uint64_t(dims[3 * b + 1]) * uint64_t(dims[3 * b + 2]);
-                const uint64_t padded = (nb + kBlockSites - 1) / kBlockSites * kBlockSites;
-                if (padded * uint64_t(L.Q) * h->elem >= (uint64_t(1) << 31)) {
-                    delete h;
-                    return fail(LBM_EINVAL, "box %d of a batch must hold less than 2 GiB of populations", b);
-                }
-            }
-        for (int b = 0; b < nbox; ++b) {
-            if (dims[3 * b + 1] > 65535 || dims[3 * b + 2] > 65535) {
-                delete h;
-                return fail(LBM_EINVAL, "box %d: ny and nz must be at most 65535", b);
-            }
-            // the batched step splits a lane's site with a float reciprocal,
-            // exact while x0 + 64 stays below 2^22
-            if (nbox > 1 && dims[3 * b] > (int64_t(1) << 21)) {
-                delete h;
-                return fail(LBM_EINVAL, "box %d of a batch: nx must be at most 2^21", b);
-            }
-        }
 
         auto cleanup = [&](lbm_status s) {
             free_all(h);

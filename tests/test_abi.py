@@ -77,6 +77,11 @@ def _create(lib, lattice, dims, tau, dtype):
     ((1, (8, -1, 8), 0.6, 1), "negative dim"),
     ((0, (8, 8, 2), 0.6, 1), "2-D lattice with nz != 1"),
     ((1, (1 << 20, 1 << 20, 1), 0.6, 1), "too many sites"),
+    ((1, (1, 65536, 1), 0.6, 1), "ny > 65535"),
+    ((1, (1, 1, 65536), 0.6, 1), "nz > 65535"),
+    ((1, (1, 65535, 65535), 0.6, 1), "ny * nz >= 2^31"),
+    ((0, (1 << 28, 1, 1), 0.6, 0), "population row of 2 GiB"),
+    ((1, (1 << 20, 256, 65535), 0.6, 2), "more than 2^36 sites"),
 ])
 def test_create_rejects_bad_arguments_on_host(lib, args, why):
     lattice, dims, tau, dtype = args
@@ -102,6 +107,29 @@ def test_batch_rejects_bad_box(lib):
     rc = lib.lbm_create_batch(ctypes.byref(h), 1, 0, dims.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                               tau.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 1)
     assert rc == -1
+
+
+def _create_batch(lib, lattice, dims, taus, dtype):
+    h = ctypes.c_void_p()
+    d = np.ascontiguousarray(dims, dtype=np.int64)
+    t = np.ascontiguousarray(taus, dtype=np.float64)
+    rc = lib.lbm_create_batch(ctypes.byref(h), lattice, len(t), d.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                              t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), dtype)
+    return rc, h
+
+
+@pytest.mark.parametrize("dims,dtype,needle", [
+    ([[1024, 1024, 14], [8, 8, 8]], 0, "2 GiB"),          # 14.7 M sites * 19 * 8 B in one batch box
+    ([[(1 << 21) + 1, 1, 1], [8, 8, 8]], 0, "2^21"),      # float-reciprocal site split of the batched step
+    ([[8, 65536, 1], [8, 8, 8]], 1, "65535"),
+])
+def test_batch_size_limits_are_host_checks(lib, dims, dtype, needle):
+    """Every documented limit of lbm_create_batch is an argument check made on
+    the host before any device call: LBM_EINVAL with or without a GPU."""
+    rc, h = _create_batch(lib, 1, dims, [0.6] * len(dims), dtype)
+    assert rc == -1
+    assert not h.value
+    assert needle in lib.lbm_last_error().decode()
 
 
 def test_null_handle_calls_are_rejected(lib):
