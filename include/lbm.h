@@ -235,6 +235,21 @@ lbm_status lbm_totals(lbm_t h, double* out);
 lbm_status lbm_residual(lbm_t h, const double* rho_ref, const double* u_ref, int32_t on_device,
                         double out[4]);
 
+/* lbm_residual for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  It
+ * calls no hipMalloc, hipFree or other allocating routine and does not
+ * synchronise: the two residual kernels are enqueued on the handle's stream.
+ * rho_ref and u_ref are device pointers (layout as for lbm_moments); out is a
+ * device pointer to 4 doubles that receives {max |du|, sqrt(sum |du|^2),
+ * max |drho|, sqrt(sum drho^2)}, the values lbm_residual returns (the square
+ * roots taken on the GPU), valid once the stream reaches that point.
+ * The per-chunk partial sums live in a 2 MiB array that the library holds on
+ * each GPU until the process ends, so a handle of at most 65536 reduction
+ * chunks of 4096 sites is accepted (2^28 sites in one box); larger handles get
+ * LBM_EINVAL.  All calls on one GPU share that array: calls that overlap on
+ * one GPU (two streams, two threads) race and give wrong results. */
+lbm_status lbm_residual_noalloc(lbm_t h, const double* rho_ref, const double* u_ref, double* out);
+
 /* Checkpoint: bytes needed by lbm_get_state (a header plus the raw stored
  * populations, Q * nstored values, padding included). */
 lbm_status lbm_checkpoint_bytes(lbm_t h, size_t* bytes);

@@ -13,6 +13,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <mutex>
 #include <new>
 #include <sstream>
 #include <utility>
@@ -68,6 +69,21 @@ struct CkptHeader {
     uint64_t reserved;  // keeps the header 64 bytes, so the payload is 64-byte aligned
 };
 static_assert(sizeof(CkptHeader) == 64, "checkpoint header layout");
+
+// Scratch of the allocation-free residual (lbm_residual_noalloc): the
+// per-chunk partial sums of the residual kernels, 4 doubles per reduction
+// chunk.  Every GPU the library runs on holds its own copy of this array for
+// the life of the process.  In host code `scratch` is only a stand-in for the
+// symbol: its device address on the current GPU comes from
+// hipGetSymbolAddress (scratch_address), and only that address is handed to
+// kernels.
+constexpr size_t kScratchBytes = size_t(2) << 20;
+constexpr int kScratchChunks = int(kScratchBytes / (4 * sizeof(double)));
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
 
 }  // namespace
 
@@ -221,6 +237,24 @@ lbm_status device_check(int* dev)
     return LBM_OK;
 }
 
+// Device address of `scratch` on GPU `dev`, which must be the current device.
+// Resolved once per device (at lbm_create) and kept; later calls only read
+// the table.
+lbm_status scratch_address(int dev, double** out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(LBM_EDEVICE, "device %d beyond the scratch table", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return fail_hip(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(LBM_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return LBM_OK;
+}
+
 // Wave tiles of the batched step (step_batch.hpp): one per 64-site block of
 // each box.  The table does not depend on the block size.
 lbm_status build_tiles(lbm_ctx* h)
@@ -293,6 +327,8 @@ lbm_status create_common(lbm_t* out, int32_t lattice, int32_t nbox, const int64_
     int dev = 0;
     lbm_status st = device_check(&dev);
     if (st != LBM_OK) return st;
+    double* scratch_ptr = nullptr;
+    if ((st = scratch_address(dev, &scratch_ptr)) != LBM_OK) return st;
 
     lbm_ctx* h = new lbm_ctx();
     // an exception (host allocation) past this point frees the handle
@@ -1078,7 +1114,7 @@ lbm_status lbm_residual(lbm_t h, const double* rho_ref, const double* u_ref, int
         bool swapped = false;
         state_view(h, &state, &swapped);
         hipError_t e = launch_residual(h->lattice, h->dtype, state, swapped, dr, du, h->d_chunks, h->nchunks,
-                                       h->d_boxes, h->nsites, h->d_partial, h->d_out, h->stream);
+                                       h->d_boxes, h->nsites, h->d_partial, h->d_out, false, h->stream);
         double tmp[4] = {0, 0, 0, 0};
         if (e == hipSuccess) e = hipMemcpyAsync(tmp, h->d_out, 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream);
         hipError_t e2 = hipStreamSynchronize(h->stream);
@@ -1095,6 +1131,34 @@ lbm_status lbm_residual(lbm_t h, const double* rho_ref, const double* u_ref, int
         return fail(LBM_ENOMEM, "lbm_residual: host memory allocation failed");
     } catch (...) {
         return fail(LBM_EDEVICE, "lbm_residual: unexpected host exception");
+    }
+}
+
+lbm_status lbm_residual_noalloc(lbm_t h, const double* rho_ref, const double* u_ref, double* out)
+{
+    try {
+        if (lbm_status st = check_handle(h)) return st;
+        if (!rho_ref || !u_ref || !out) return fail(LBM_EINVAL, "NULL argument");
+        if (h->nchunks > kScratchChunks)
+            return fail(LBM_EINVAL,
+                        "lbm_residual_noalloc: %lld sites need %d reduction chunks; the scratch holds %d (%d sites "
+                        "per chunk, %zu bytes); use lbm_residual",
+                        (long long)h->nsites, h->nchunks, kScratchChunks, kChunkSites, kScratchBytes);
+        if (!h->initialized) return fail(LBM_ESTATE, "lbm_residual_noalloc before lbm_init");
+        HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+        double* partial = nullptr;
+        if (lbm_status st = scratch_address(h->device, &partial)) return st;
+        const void* state = nullptr;
+        bool swapped = false;
+        state_view(h, &state, &swapped);
+        // every partial slot the final kernel reads is written first by this
+        // call, so nothing needs clearing
+        hipError_t e = launch_residual(h->lattice, h->dtype, state, swapped, rho_ref, u_ref, h->d_chunks, h->nchunks,
+                                       h->d_boxes, h->nsites, partial, out, true, h->stream);
+        if (e != hipSuccess) return fail_hip(e, "residual kernels");
+        return LBM_OK;
+    } catch (...) {
+        return fail(LBM_EDEVICE, "lbm_residual_noalloc: unexpected host exception");
     }
 }
 

@@ -106,9 +106,12 @@ hipError_t launch_moments(int lat, int dtype, const void* src, bool swapped, dou
 hipError_t launch_totals(int lat, int dtype, const void* src, bool swapped, const ChunkDesc* chunks, int nchunks,
                          const int* box_chunk_begin, int nbox, const BoxDesc* boxes, double* partial, double* out,
                          hipStream_t s);
+// Error residuals: partial holds 4 doubles per chunk; out gets {max |du|,
+// sum du^2, max |drho|, sum drho^2}, or the square roots of the two sums when
+// sqrt_l2.
 hipError_t launch_residual(int lat, int dtype, const void* src, bool swapped, const double* rho_ref,
                            const double* u_ref, const ChunkDesc* chunks, int nchunks, const BoxDesc* boxes,
-                           long long nsites, double* partial, double* out, hipStream_t s);
+                           long long nsites, double* partial, double* out, bool sqrt_l2, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 
 // Host copy of a lattice's tables (from the compile-time descriptors).

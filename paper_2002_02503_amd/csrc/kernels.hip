@@ -251,8 +251,10 @@ __global__ __launch_bounds__(kRedBlock) void k_residual_partial(const S* __restr
         for (int k = 0; k < 4; ++k) partial[blockIdx.x * 4 + k] = acc[k];
 }
 
+// sqrt_l2: write the square roots of the two sums (the L2 norms) instead of
+// the sums themselves.
 __global__ __launch_bounds__(kRedBlock) void k_residual_final(const double* __restrict__ partial, int nchunks,
-                                                              double* __restrict__ out)
+                                                              double* __restrict__ out, int sqrt_l2)
 {
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int c = threadIdx.x; c < nchunks; c += kRedBlock) {
@@ -263,9 +265,12 @@ __global__ __launch_bounds__(kRedBlock) void k_residual_final(const double* __re
     }
     const bool is_max[4] = {true, false, true, false};
     block_tree<4>(acc, is_max);
-    if (threadIdx.x == 0)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) out[k] = acc[k];
+    if (threadIdx.x == 0) {
+        out[0] = acc[0];
+        out[1] = sqrt_l2 ? sqrt(acc[1]) : acc[1];
+        out[2] = acc[2];
+        out[3] = sqrt_l2 ? sqrt(acc[3]) : acc[3];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -326,7 +331,7 @@ hipError_t launch_totals(int lat, int dtype, const void* src, bool swapped, cons
 
 hipError_t launch_residual(int lat, int dtype, const void* src, bool swapped, const double* rho_ref,
                            const double* u_ref, const ChunkDesc* chunks, int nchunks, const BoxDesc* boxes,
-                           long long nsites, double* partial, double* out, hipStream_t s)
+                           long long nsites, double* partial, double* out, bool sqrt_l2, hipStream_t s)
 {
     return dispatch_ld(lat, dtype, [&](auto Lt, auto* Sp, auto) -> hipError_t {
         using L = decltype(Lt);
@@ -339,7 +344,7 @@ hipError_t launch_residual(int lat, int dtype, const void* src, bool swapped, co
                                                                           chunks, boxes, nsites, partial);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        k_residual_final<<<1, kRedBlock, 0, s>>>(partial, nchunks, out);
+        k_residual_final<<<1, kRedBlock, 0, s>>>(partial, nchunks, out, sqrt_l2 ? 1 : 0);
         return hipGetLastError();
     });
 }

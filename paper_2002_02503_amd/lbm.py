@@ -28,7 +28,7 @@ STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE", -4
 EXPORTS = ["lbm_create", "lbm_create_batch", "lbm_set_hermite_order", "lbm_set_collision", "lbm_set_stream",
            "lbm_state_bytes",
            "lbm_bind_state", "lbm_init", "lbm_step", "lbm_prepare", "lbm_set_graph_chunk", "lbm_set_launch",
-           "lbm_set_kernel", "lbm_tune", "lbm_moments", "lbm_totals", "lbm_residual", "lbm_checkpoint_bytes", "lbm_get_state",
+           "lbm_set_kernel", "lbm_tune", "lbm_moments", "lbm_totals", "lbm_residual", "lbm_residual_noalloc", "lbm_checkpoint_bytes", "lbm_get_state",
            "lbm_set_state", "lbm_get_info", "lbm_sync", "lbm_destroy", "lbm_last_error", "lbm_lattice_table",
            "lbm_copy_probe"]
 
@@ -92,6 +92,7 @@ def load_library() -> ctypes.CDLL:
         "lbm_moments": [vp, vp, vp, ctypes.c_int32],
         "lbm_totals": [vp, dp],
         "lbm_residual": [vp, vp, vp, ctypes.c_int32, dp],
+        "lbm_residual_noalloc": [vp, vp, vp, vp],
         "lbm_checkpoint_bytes": [vp, ctypes.POINTER(ctypes.c_size_t)],
         "lbm_get_state": [vp, vp, ctypes.c_size_t],
         "lbm_set_state": [vp, vp, ctypes.c_size_t],
@@ -324,6 +325,17 @@ class Simulation:
         out = np.zeros(4)
         _check(self.lib.lbm_residual(self.h, pr, pu, dev, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return {"u_max": out[0], "u_l2": out[1], "rho_max": out[2], "rho_l2": out[3]}
+
+    def residual_noalloc(self, rho_ref, u_ref, out):
+        """lbm_residual_noalloc: all three are contiguous float64 CUDA tensors
+        (out holds 4 values); nothing is allocated and nothing synchronises."""
+        pr, dr = _ptr_of(rho_ref)
+        pu, du = _ptr_of(u_ref)
+        po, do = _ptr_of(out)
+        if not (dr and du and do) or out.numel() < 4:
+            raise TypeError("rho_ref, u_ref and out must be device tensors; out holds 4 values")
+        _check(self.lib.lbm_residual_noalloc(self.h, pr, pu, po))
+        return out
 
     def get_state(self) -> np.ndarray:
         n = ctypes.c_size_t()
