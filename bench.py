@@ -74,8 +74,9 @@ def timed_steps(sim, steps: int, warmup: int) -> float:
     return e0.elapsed_time(e1) / steps
 
 
-KERNEL_NAMES = {1: "scalar", 2: "row_wave", 3: "in_place", 4: "two_row"}
-KERNEL_SYMBOLS = {"scalar": "k_step", "row_wave": "k_step_vec", "in_place": "k_step_ip", "two_row": "k_step_pair"}
+KERNEL_NAMES = {1: "scalar", 2: "row_wave", 3: "in_place", 4: "two_row", 5: "twist"}
+KERNEL_SYMBOLS = {"scalar": "k_step", "row_wave": "k_step_vec", "in_place": "k_step_ip", "two_row": "k_step_pair",
+                  "twist": "k_step_tw"}
 
 
 def measure_box(lattice, dims, tau, dtype, rho, u, steps, warmup, tune=True, **kw):
@@ -219,7 +220,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle leg (CPU baseline timing and error statements)")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle stepping")
-    ap.add_argument("--kernel", choices=["tune", "scalar", "row_wave", "in_place", "two_row"], default="tune",
+    ap.add_argument("--kernel", choices=["tune", "scalar", "row_wave", "in_place", "two_row", "twist"],
+                    default="tune",
                     help="headline step kernel: autotuned (default) or pinned")
     ap.add_argument("--block", type=int, default=256, help="threads per block when --kernel is pinned")
     ap.add_argument("--dtype", choices=["fp32", "fp16", "bf16"], default="fp32",

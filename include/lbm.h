@@ -75,8 +75,12 @@ typedef enum {
     LBM_KERNEL_IN_PLACE = 3,  /* one site per thread on one buffer: each step reads and writes the same
                                  elements, alternating between two layouts of the state (bit-identical
                                  results, half the memory) */
-    LBM_KERNEL_TWO_ROW = 4    /* two sites per thread (rows 2j and 2j+1, ny even): the second site's loads
+    LBM_KERNEL_TWO_ROW = 4,   /* two sites per thread (rows 2j and 2j+1, ny even): the second site's loads
                                  are in flight while the first collides (bit-identical results) */
+    LBM_KERNEL_TWIST = 5      /* in place on one buffer with the twisted layouts: every step reads and
+                                 writes each element once, only at the cells x + b (b the positive part
+                                 of a velocity), so it touches fewer row tiles (bit-identical results,
+                                 half the memory) */
 } lbm_kernel;
 
 typedef struct {
@@ -197,18 +201,25 @@ lbm_status lbm_set_launch(lbm_t h, int32_t block, int32_t grid);
  * allocates the second buffer.  Batches always use the batched kernel (one
  * wave per 64-site block); for them LBM_KERNEL_AUTO and LBM_KERNEL_SCALAR are
  * accepted and the other variants are LBM_EINVAL.
+ * LBM_KERNEL_TWIST (single box) also steps inside one buffer.  The state is
+ * kept in twisted layouts: population i of site x sits at site x + b_i, b_i
+ * the positive part of c_i component by component, in tile row m(i) after an
+ * even number of its steps and m(opp(i)) after an odd number.  lbm_init and
+ * lbm_set_state write that layout; the readers and lbm_get_state handle it as
+ * they handle the swapped one.
  * LBM_KERNEL_TWO_ROW needs a single box with ny even (else LBM_EINVAL).
  * May be called at any time: on an initialised handle the state is first
- * brought to the natural layout (which may allocate the second buffer), and
- * the run continues bit for bit. */
+ * brought to the natural layout and then into the new kernel's starting
+ * layout (which may allocate the second buffer), and the run continues bit
+ * for bit. */
 lbm_status lbm_set_kernel(lbm_t h, int32_t kernel);
 
 /* Autotune the step's launch: time every candidate over `steps` steps with HIP
  * events, in three interleaved rounds, and keep the candidate with the fastest
  * round.  Single box: the scalar step at 64/128/256 threads per block, the
- * in-place step and the two-row step (ny even) at 256, the scalar and in-place
- * steps at one whole x-row per block when nx rounds up to 192 lanes, and the
- * row-wave step where it applies.  Batch: 64/128/256 threads per block, with
+ * in-place, twist and two-row (ny even) steps at 256, the scalar, in-place
+ * and twist steps at one whole x-row per block when nx rounds up to 192 lanes,
+ * and the row-wave step where it applies.  Batch: 64/128/256 threads per block, with
  * one wave per 64-site block of the layout or 1024/2048/4096 persistent
  * blocks.  The state is saved before and restored after, so t and the
  * populations are unchanged (all candidates compute the same bits).  Choices are appended to the text file `cache_path` (NULL: the

@@ -437,7 +437,7 @@ lbm_status ensure_buffers(lbm_ctx* h)
 {
     if (!h->buf[0])
         if (lbm_status st = alloc_buffer(h, 0)) return st;
-    const bool one = is_single(h) && h->kernel == LBM_KERNEL_IN_PLACE;
+    const bool one = is_single(h) && (h->kernel == LBM_KERNEL_IN_PLACE || h->kernel == LBM_KERNEL_TWIST);
     if (!h->buf[1] && !one)
         if (lbm_status st = alloc_buffer(h, 1)) return st;
     return LBM_OK;
@@ -450,6 +450,18 @@ lbm_status ensure_second(lbm_ctx* h)
 }
 
 bool in_place(const lbm_ctx* h) { return is_single(h) && effective_kernel(h) == LBM_KERNEL_IN_PLACE; }
+bool twisted(const lbm_ctx* h) { return is_single(h) && effective_kernel(h) == LBM_KERNEL_TWIST; }
+// The step works inside one buffer (either in-place form).
+bool one_buffer(const lbm_ctx* h) { return in_place(h) || twisted(h); }
+
+// Layout of the current state (StateLayout): the in-place forms alternate
+// two layouts, h->cur being the parity of the steps they took.
+int state_layout(const lbm_ctx* h)
+{
+    if (in_place(h)) return h->cur == 1 ? kSwapped : kNatural;
+    if (twisted(h)) return h->cur == 1 ? kTwistOdd : kTwistEven;
+    return kNatural;
+}
 
 // The padding sites of a batch's blocked layout are never read or written by
 // the step; zero them in both buffers (before lbm_init or lbm_set_state writes
@@ -475,13 +487,17 @@ StepGeom single_geom(const lbm_ctx* h, int block)
 
 // One step on stream s.  Two-buffer kernels step from buf[parity] into
 // buf[parity ^ 1].  The in-place kernel steps buf[0] from the natural layout
-// (parity 0) to the swapped one, or back (parity 1).  Either way the next
-// step has parity ^ 1, which h->cur tracks.
+// (parity 0) to the swapped one, or back (parity 1); the twist kernel steps
+// buf[0] from the twisted layout of an even time (parity 0) or an odd one.
+// Either way the next step has parity ^ 1, which h->cur tracks.
 hipError_t launch_one(lbm_ctx* h, int parity, hipStream_t s)
 {
     const int block = effective_block(h);
     if (in_place(h))
         return launch_step_ip(h->lattice, h->dtype, h->K, step_kind(h), h->buf[0], parity == 0, single_geom(h, block),
+                              1.0 - 1.0 / h->tau[0], h->theta, block, s);
+    if (twisted(h))
+        return launch_step_tw(h->lattice, h->dtype, h->K, step_kind(h), h->buf[0], parity == 0, single_geom(h, block),
                               1.0 - 1.0 / h->tau[0], h->theta, block, s);
     const void* src = h->buf[parity];
     void* dst = h->buf[parity ^ 1];
@@ -504,58 +520,88 @@ hipError_t launch_one(lbm_ctx* h, int parity, hipStream_t s)
                              block, h->grid, h->aligned_rows, s);
 }
 
-// Where the current state is, and whether the in-place step left it in the
-// swapped layout (after an odd number of its steps).
-void state_view(const lbm_ctx* h, const void** state, bool* swapped)
+// Where the current state is, and in which layout (StateLayout).
+void state_view(const lbm_ctx* h, const void** state, int* layout)
 {
-    if (in_place(h)) {
-        *state = h->buf[0];
-        *swapped = (h->cur == 1);
-    } else {
-        *state = h->buf[h->cur];
-        *swapped = false;
-    }
+    *layout = state_layout(h);
+    *state = one_buffer(h) ? h->buf[0] : h->buf[h->cur];
 }
 
-// Bring the state into buf[0] in the natural layout (cur = 0), valid for
-// every step kernel, before the kernel choice changes on an initialised
-// handle: undo the swap of the in-place step into the other buffer, then swap
-// the two buffer pointers.
+// Bring the state into buf[0] in the natural layout (cur = 0), before the
+// kernel choice changes on an initialised handle: rearrange an in-place
+// layout into the other buffer, or take the two-buffer state from buf[1],
+// then swap the two buffer pointers.  Every kernel but the twist step can
+// start from there (enter_kernel_layout prepares that one).
 lbm_status canonicalize(lbm_ctx* h)
 {
-    if (!h->initialized || h->cur == 0) return LBM_OK;
-    if (in_place(h)) {
+    if (!h->initialized) return LBM_OK;
+    const int layout = state_layout(h);
+    if (layout == kNatural && (one_buffer(h) || h->cur == 0)) return LBM_OK;
+    if (layout != kNatural) {
         if (lbm_status st = ensure_second(h)) return st;
         const int block = effective_block(h);
-        hipError_t e =
-            launch_unswap(h->lattice, h->dtype, h->buf[0], h->buf[1], single_geom(h, block), block, h->stream);
-        if (e != hipSuccess) return fail_hip(e, "unswap kernel");
+        hipError_t e = launch_relayout(h->lattice, h->dtype, layout, true, h->buf[0], h->buf[1],
+                                       single_geom(h, block), block, h->stream);
+        if (e != hipSuccess) return fail_hip(e, "relayout kernel");
     }
+    std::swap(h->buf[0], h->buf[1]);
+    h->cur = 0;
+    // the natural state at cur = 0 is the scalar step's starting point, not
+    // the twist step's; callers choose the next kernel right after
+    if (twisted(h)) h->kernel = LBM_KERNEL_SCALAR;
+    drop_graphs(h);
+    return LBM_OK;
+}
+
+// After a kernel change on an initialised handle (state natural in buf[0],
+// cur = 0): put the state into the layout the new kernel starts from.  Only
+// the twist kernel needs it (its even-time layout).
+lbm_status enter_kernel_layout(lbm_ctx* h)
+{
+    if (!h->initialized || !twisted(h)) return LBM_OK;
+    if (lbm_status st = ensure_second(h)) return st;
+    const int block = effective_block(h);
+    hipError_t e = launch_relayout(h->lattice, h->dtype, kTwistEven, false, h->buf[0], h->buf[1],
+                                   single_geom(h, block), block, h->stream);
+    if (e != hipSuccess) return fail_hip(e, "relayout kernel");
     std::swap(h->buf[0], h->buf[1]);
     h->cur = 0;
     drop_graphs(h);
     return LBM_OK;
 }
 
-// Host copy of the swapped layout -> natural layout (single box): population
-// j of site x comes from site x + c_j, tile row m(opp(j)).
-void unswap_host(const lbm_ctx* h, const char* src, char* dst)
+// Host copy of a single box's state between an in-place layout and the
+// natural one (to_natural: src in `layout`, dst natural; else the reverse).
+// Population i of site x is at x + o_i, tile row r_i: o_i = c_i, r_i =
+// m(opp(i)) when swapped; o_i = b_i (positive part of c_i), r_i = m(i) or
+// m(opp(i)) when twisted at an even or odd time.
+void relayout_host(const lbm_ctx* h, int layout, bool to_natural, const char* src, char* dst)
 {
     const LatticeInfo& L = h->lat;
     const int64_t nx = h->dims[0], ny = h->dims[1], nz = h->dims[2];
     const size_t e = h->elem;
     const int64_t tile = int64_t(L.Q) * nx;
     auto wrap = [](int64_t v, int64_t n) { return ((v % n) + n) % n; };
-    for (int64_t z = 0; z < nz; ++z)
-        for (int64_t y = 0; y < ny; ++y)
-            for (int j = 0; j < L.Q; ++j) {
-                const int jo = (j == 0) ? 0 : ((j & 1) ? j + 1 : j - 1);
-                const int64_t zs = wrap(z + L.c[j * 3 + 2], nz), ys = wrap(y + L.c[j * 3 + 1], ny);
-                const char* s_row = src + ((zs * ny + ys) * tile + int64_t(L.mrow[jo]) * nx) * e;
-                char* d_row = dst + ((z * ny + y) * tile + int64_t(L.mrow[j]) * nx) * e;
-                for (int64_t x = 0; x < nx; ++x)
-                    std::memcpy(d_row + x * e, s_row + wrap(x + L.c[j * 3], nx) * e, e);
+    for (int j = 0; j < L.Q; ++j) {
+        const int jo = (j == 0) ? 0 : ((j & 1) ? j + 1 : j - 1);
+        int64_t o[3];
+        for (int a = 0; a < 3; ++a) {
+            const int c = L.c[j * 3 + a];
+            o[a] = (layout == kSwapped) ? c : (c > 0 ? c : 0);
+        }
+        const int64_t r = (layout == kTwistEven) ? L.mrow[j] : L.mrow[jo];
+        for (int64_t z = 0; z < nz; ++z)
+            for (int64_t y = 0; y < ny; ++y) {
+                const int64_t zs = wrap(z + o[2], nz), ys = wrap(y + o[1], ny);
+                const int64_t lay_row = (zs * ny + ys) * tile + r * nx;
+                const int64_t nat_row = (z * ny + y) * tile + int64_t(L.mrow[j]) * nx;
+                for (int64_t x = 0; x < nx; ++x) {
+                    const int64_t xs = wrap(x + o[0], nx);
+                    if (to_natural) std::memcpy(dst + (nat_row + x) * e, src + (lay_row + xs) * e, e);
+                    else std::memcpy(dst + (lay_row + xs) * e, src + (nat_row + x) * e, e);
+                }
             }
+    }
 }
 
 lbm_status build_graph(lbm_ctx* h, int parity)
@@ -761,10 +807,10 @@ lbm_status lbm_set_kernel(lbm_t h, int32_t kernel)
     try {
         if (lbm_status st = check_handle(h)) return st;
         if (kernel != LBM_KERNEL_AUTO && kernel != LBM_KERNEL_SCALAR && kernel != LBM_KERNEL_ROW_WAVE &&
-            kernel != LBM_KERNEL_IN_PLACE && kernel != LBM_KERNEL_TWO_ROW)
+            kernel != LBM_KERNEL_IN_PLACE && kernel != LBM_KERNEL_TWO_ROW && kernel != LBM_KERNEL_TWIST)
             return fail(LBM_EINVAL, "unknown kernel variant %d", kernel);
-        if (kernel == LBM_KERNEL_IN_PLACE && !is_single(h))
-            return fail(LBM_EINVAL, "the in-place step is for a single box; batches use the tiled batched kernel");
+        if ((kernel == LBM_KERNEL_IN_PLACE || kernel == LBM_KERNEL_TWIST) && !is_single(h))
+            return fail(LBM_EINVAL, "the in-place steps are for a single box; batches use the tiled batched kernel");
         if (kernel == LBM_KERNEL_TWO_ROW && (!is_single(h) || h->dims[1] % 2 != 0))
             return fail(LBM_EINVAL, "the two-row step needs a single box with ny even");
         if (kernel == LBM_KERNEL_ROW_WAVE && !row_wave_sites(h))
@@ -775,7 +821,7 @@ lbm_status lbm_set_kernel(lbm_t h, int32_t kernel)
         if (lbm_status st = canonicalize(h)) return st;
         h->kernel = kernel;
         drop_graphs(h);
-        return LBM_OK;
+        return enter_kernel_layout(h);
     } catch (const std::bad_alloc&) {
         return fail(LBM_ENOMEM, "lbm_set_kernel: host memory allocation failed");
     } catch (...) {
@@ -800,7 +846,8 @@ lbm_status lbm_init(lbm_t h, const double* rho, const double* u, int32_t on_devi
             if (t1) (void)hipFree(drho);
             return st;
         }
-        hipError_t e = launch_init(h->lattice, h->dtype, h->K, drho, du, h->buf[0], h->d_chunks, h->nchunks, h->d_boxes,
+        hipError_t e = launch_init(h->lattice, h->dtype, h->K, twisted(h) ? kTwistEven : kNatural, drho, du, h->buf[0],
+                                   h->d_chunks, h->nchunks, h->d_boxes,
                                    h->nsites, h->stream);
         hipError_t e2 = hipStreamSynchronize(h->stream);
         if (t1) (void)hipFree(drho);
@@ -824,7 +871,7 @@ lbm_status lbm_prepare(lbm_t h)
         if (lbm_status st = check_handle(h)) return st;
         if (!h->initialized) return fail(LBM_ESTATE, "lbm_prepare before lbm_init");
         HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
-        if (!in_place(h))
+        if (!one_buffer(h))
             if (lbm_status st = ensure_second(h)) return st;
         for (int p = 0; p < 2; ++p)
             if (lbm_status st = build_graph(h, p)) return st;
@@ -844,7 +891,7 @@ lbm_status lbm_step(lbm_t h, int64_t n)
         if (!h->initialized) return fail(LBM_ESTATE, "lbm_step before lbm_init");
         if (n == 0) return LBM_OK;
         HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
-        if (!in_place(h))
+        if (!one_buffer(h))
             if (lbm_status st = ensure_second(h)) return st;
         if (lbm_status st = build_tiles(h)) return st;
         const int G = h->graph_chunk;
@@ -924,7 +971,7 @@ lbm_status apply_choice(lbm_ctx* h, const LaunchChoice& c)
     h->block = c.block;
     h->grid = c.grid;
     drop_graphs(h);
-    return LBM_OK;
+    return enter_kernel_layout(h);
 }
 
 }  // namespace
@@ -942,11 +989,12 @@ lbm_status lbm_tune(lbm_t h, int32_t steps, const char* cache_path)
         LaunchChoice best;
         if (cache_lookup(cache_path, key, &best)) {
             // the cache is a text file: take only values this library can launch
-            if (best.kernel < LBM_KERNEL_AUTO || best.kernel > LBM_KERNEL_TWO_ROW) best.kernel = LBM_KERNEL_SCALAR;
+            if (best.kernel < LBM_KERNEL_AUTO || best.kernel > LBM_KERNEL_TWIST) best.kernel = LBM_KERNEL_SCALAR;
             if (!(best.block == 0 || (best.block >= 64 && best.block <= 256 && best.block % 64 == 0))) best.block = 0;
             if (best.grid < 0) best.grid = 0;
             if (best.kernel == LBM_KERNEL_ROW_WAVE && !row_wave_sites(h)) best.kernel = LBM_KERNEL_SCALAR;
-            if (best.kernel == LBM_KERNEL_IN_PLACE && !is_single(h)) best.kernel = LBM_KERNEL_SCALAR;
+            if ((best.kernel == LBM_KERNEL_IN_PLACE || best.kernel == LBM_KERNEL_TWIST) && !is_single(h))
+                best.kernel = LBM_KERNEL_SCALAR;
             if (best.kernel == LBM_KERNEL_TWO_ROW && (!is_single(h) || h->dims[1] % 2 != 0))
                 best.kernel = LBM_KERNEL_SCALAR;
             return apply_choice(h, best);
@@ -957,6 +1005,7 @@ lbm_status lbm_tune(lbm_t h, int32_t steps, const char* cache_path)
         if (is_single(h)) {
             for (int b : {64, 128, 256}) cand.push_back({LBM_KERNEL_SCALAR, b, 0});
             cand.push_back({LBM_KERNEL_IN_PLACE, 256, 0});
+            cand.push_back({LBM_KERNEL_TWIST, 256, 0});
             // a block of one whole x-row (nx rounded up to 64 lanes) when that
             // is none of the above: the x-shifted lines then stay within one
             // workgroup (one L2) instead of being fetched by neighbouring ones
@@ -964,6 +1013,7 @@ lbm_status lbm_tune(lbm_t h, int32_t steps, const char* cache_path)
             if (row < 256 && row != 64 && row != 128) {
                 cand.push_back({LBM_KERNEL_SCALAR, int(row), 0});
                 cand.push_back({LBM_KERNEL_IN_PLACE, int(row), 0});
+                cand.push_back({LBM_KERNEL_TWIST, int(row), 0});
             }
             if (h->dims[1] % 2 == 0) cand.push_back({LBM_KERNEL_TWO_ROW, 256, 0});
             if (row_wave_sites(h)) cand.push_back({LBM_KERNEL_ROW_WAVE, 0, 0});
@@ -1014,6 +1064,9 @@ lbm_status lbm_tune(lbm_t h, int32_t steps, const char* cache_path)
         (void)hipFree(saved);
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
+        // buf[0] holds the saved natural state again, which is the state of
+        // the scalar step at cur = 0 (the twist step's even layout is not)
+        h->kernel = LBM_KERNEL_SCALAR;
         h->cur = cur0;
         h->t = t0;
         if (st != LBM_OK) {
@@ -1046,9 +1099,9 @@ lbm_status lbm_moments(lbm_t h, double* rho, double* u, int32_t on_device)
             du = drho + n;
         }
         const void* state = nullptr;
-        bool swapped = false;
-        state_view(h, &state, &swapped);
-        hipError_t e = launch_moments(h->lattice, h->dtype, state, swapped, drho, du, h->d_chunks, h->nchunks,
+        int layout = kNatural;
+        state_view(h, &state, &layout);
+        hipError_t e = launch_moments(h->lattice, h->dtype, state, layout, drho, du, h->d_chunks, h->nchunks,
                                       h->d_boxes, h->nsites, h->stream);
         if (e == hipSuccess && !on_device) {
             e = hipMemcpyAsync(rho, drho, n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
@@ -1074,9 +1127,9 @@ lbm_status lbm_totals(lbm_t h, double* out)
         if (!h->initialized) return fail(LBM_ESTATE, "lbm_totals before lbm_init");
         HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
         const void* state = nullptr;
-        bool swapped = false;
-        state_view(h, &state, &swapped);
-        hipError_t e = launch_totals(h->lattice, h->dtype, state, swapped, h->d_chunks, h->nchunks,
+        int layout = kNatural;
+        state_view(h, &state, &layout);
+        hipError_t e = launch_totals(h->lattice, h->dtype, state, layout, h->d_chunks, h->nchunks,
                                      h->d_box_chunk_begin, h->nbox, h->d_boxes, h->d_partial, h->d_out, h->stream);
         if (e != hipSuccess) return fail_hip(e, "totals kernels");
         HIP_TRY(hipMemcpyAsync(out, h->d_out, size_t(h->nbox) * 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream),
@@ -1111,9 +1164,9 @@ lbm_status lbm_residual(lbm_t h, const double* rho_ref, const double* u_ref, int
             return st;
         }
         const void* state = nullptr;
-        bool swapped = false;
-        state_view(h, &state, &swapped);
-        hipError_t e = launch_residual(h->lattice, h->dtype, state, swapped, dr, du, h->d_chunks, h->nchunks,
+        int layout = kNatural;
+        state_view(h, &state, &layout);
+        hipError_t e = launch_residual(h->lattice, h->dtype, state, layout, dr, du, h->d_chunks, h->nchunks,
                                        h->d_boxes, h->nsites, h->d_partial, h->d_out, false, h->stream);
         double tmp[4] = {0, 0, 0, 0};
         if (e == hipSuccess) e = hipMemcpyAsync(tmp, h->d_out, 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream);
@@ -1149,11 +1202,11 @@ lbm_status lbm_residual_noalloc(lbm_t h, const double* rho_ref, const double* u_
         double* partial = nullptr;
         if (lbm_status st = scratch_address(h->device, &partial)) return st;
         const void* state = nullptr;
-        bool swapped = false;
-        state_view(h, &state, &swapped);
+        int layout = kNatural;
+        state_view(h, &state, &layout);
         // every partial slot the final kernel reads is written first by this
         // call, so nothing needs clearing
-        hipError_t e = launch_residual(h->lattice, h->dtype, state, swapped, rho_ref, u_ref, h->d_chunks, h->nchunks,
+        hipError_t e = launch_residual(h->lattice, h->dtype, state, layout, rho_ref, u_ref, h->d_chunks, h->nchunks,
                                        h->d_boxes, h->nsites, partial, out, true, h->stream);
         if (e != hipSuccess) return fail_hip(e, "residual kernels");
         return LBM_OK;
@@ -1199,15 +1252,16 @@ lbm_status lbm_get_state(lbm_t h, void* buf, size_t bytes)
         std::memcpy(buf, &hd, sizeof(hd));
         char* dst = static_cast<char*>(buf) + sizeof(hd);
         const void* state = nullptr;
-        bool swapped = false;
-        state_view(h, &state, &swapped);
+        int layout = kNatural;
+        state_view(h, &state, &layout);
         const size_t payload = size_t(h->lat.Q) * size_t(h->nstored) * h->elem;
-        if (!swapped) {
+        if (layout == kNatural) {
             HIP_TRY(hipMemcpyAsync(dst, state, payload, hipMemcpyDeviceToHost, h->stream), "copy state to host");
             HIP_TRY(hipStreamSynchronize(h->stream), "get_state synchronize");
         } else {
-            // the in-place step left the state swapped: copy it out as it is and
-            // put it into the natural layout on the host (no second device buffer)
+            // an in-place step left the state in one of its layouts: copy it out
+            // as it is and put it into the natural layout on the host (no second
+            // device buffer)
             std::vector<char> tmp;
             try {
                 tmp.resize(payload);
@@ -1216,7 +1270,7 @@ lbm_status lbm_get_state(lbm_t h, void* buf, size_t bytes)
             }
             HIP_TRY(hipMemcpyAsync(tmp.data(), state, payload, hipMemcpyDeviceToHost, h->stream), "copy state to host");
             HIP_TRY(hipStreamSynchronize(h->stream), "get_state synchronize");
-            unswap_host(h, tmp.data(), dst);
+            relayout_host(h, layout, true, tmp.data(), dst);
         }
         return LBM_OK;
     } catch (const std::bad_alloc&) {
@@ -1244,9 +1298,20 @@ lbm_status lbm_set_state(lbm_t h, const void* buf, size_t bytes)
         if (lbm_status st = build_tiles(h)) return st;
         const char* src = static_cast<const char*>(buf) + sizeof(hd);
         if (lbm_status st = clear_padding(h)) return st;
-        HIP_TRY(hipMemcpyAsync(h->buf[0], src, size_t(h->lat.Q) * size_t(h->nstored) * h->elem, hipMemcpyHostToDevice,
-                               h->stream),
-                "copy state to device");
+        const size_t payload = size_t(h->lat.Q) * size_t(h->nstored) * h->elem;
+        std::vector<char> tmp;
+        if (twisted(h)) {
+            // the twist step starts from its even-time layout: rearrange the
+            // natural checkpoint on the host (no second device buffer)
+            try {
+                tmp.resize(payload);
+            } catch (const std::bad_alloc&) {
+                return fail(LBM_ENOMEM, "host staging for the checkpoint");
+            }
+            relayout_host(h, kTwistEven, false, src, tmp.data());
+            src = tmp.data();
+        }
+        HIP_TRY(hipMemcpyAsync(h->buf[0], src, payload, hipMemcpyHostToDevice, h->stream), "copy state to device");
         HIP_TRY(hipStreamSynchronize(h->stream), "set_state synchronize");
         h->cur = 0;
         h->t = hd.t;

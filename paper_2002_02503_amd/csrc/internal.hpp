@@ -74,8 +74,19 @@ struct ChunkDesc {
     int box;
 };
 
+// Where a single box's populations are, as the step kernels leave them.
+//   kNatural:   population i of site x in its own row tile, tile row m(i)
+//               (every batch, and the two-buffer single-box steps);
+//   kSwapped:   at site x + c_i, tile row m(opp(i)) (k_step_ip after an odd
+//               number of its steps);
+//   kTwistEven: at site x + b_i, b_i the positive part of c_i, tile row m(i)
+//               (k_step_tw after an even number of its steps);
+//   kTwistOdd:  at site x + b_i, tile row m(opp(i)) (k_step_tw, odd).
+enum StateLayout : int { kNatural = 0, kSwapped = 1, kTwistEven = 2, kTwistOdd = 3 };
+
 // Kernel launchers (kernels.hip).  All return hipSuccess or the first error.
-hipError_t launch_init(int lat, int dtype, int K, const double* rho, const double* u, void* dst,
+// layout: kNatural, or kTwistEven for a single box stepped by k_step_tw.
+hipError_t launch_init(int lat, int dtype, int K, int layout, const double* rho, const double* u, void* dst,
                        const ChunkDesc* chunks, int nchunks, const BoxDesc* boxes, long long nsites,
                        hipStream_t s);
 // The fused step.  kind: collision kind (collide.hpp: 0 filtered, 1 BGK,
@@ -87,9 +98,14 @@ hipError_t launch_step(int lat, int dtype, int K, int kind, const void* src, voi
 // (from_natural) or back (step.hpp, k_step_ip).
 hipError_t launch_step_ip(int lat, int dtype, int K, int kind, void* buf, bool from_natural, const StepGeom& geo,
                           double omega, double theta, int block, hipStream_t s);
-// Swapped layout -> natural layout into another buffer (bit-exact permutation).
-hipError_t launch_unswap(int lat, int dtype, const void* src, void* dst, const StepGeom& geo, int block,
-                         hipStream_t s);
+// The in-place step on the twisted layouts, from an even time (even) or an
+// odd one (step.hpp, k_step_tw).
+hipError_t launch_step_tw(int lat, int dtype, int K, int kind, void* buf, bool even, const StepGeom& geo,
+                          double omega, double theta, int block, hipStream_t s);
+// A single box's state from `layout` to the natural layout (to_natural) or
+// back, into another buffer (bit-exact permutation).
+hipError_t launch_relayout(int lat, int dtype, int layout, bool to_natural, const void* src, void* dst,
+                           const StepGeom& geo, int block, hipStream_t s);
 // Sites per lane of the row-wave kernel for (lattice, dtype), 0 if that pair
 // has no row-wave form (a velocity component as large as V).
 int vec_sites_per_lane(int lat, int dtype);
@@ -99,17 +115,17 @@ hipError_t launch_step_vec(int lat, int dtype, int K, int kind, const void* src,
 // multiple of 64, so populations with c_x = 0 are read in whole blocks.
 hipError_t launch_step_batch(int lat, int dtype, int K, int kind, const void* src, void* dst, const TileDesc* tiles,
                              int ntiles, double theta, int block, int grid, bool aligned_rows, hipStream_t s);
-// Readers of the stored state.  swapped: the state is in the swapped layout
-// the in-place step leaves after an odd number of steps (single box).
-hipError_t launch_moments(int lat, int dtype, const void* src, bool swapped, double* rho, double* u,
+// Readers of the stored state, in any StateLayout (the in-place layouts for
+// a single box only).
+hipError_t launch_moments(int lat, int dtype, const void* src, int layout, double* rho, double* u,
                           const ChunkDesc* chunks, int nchunks, const BoxDesc* boxes, long long nsites, hipStream_t s);
-hipError_t launch_totals(int lat, int dtype, const void* src, bool swapped, const ChunkDesc* chunks, int nchunks,
+hipError_t launch_totals(int lat, int dtype, const void* src, int layout, const ChunkDesc* chunks, int nchunks,
                          const int* box_chunk_begin, int nbox, const BoxDesc* boxes, double* partial, double* out,
                          hipStream_t s);
 // Error residuals: partial holds 4 doubles per chunk; out gets {max |du|,
 // sum du^2, max |drho|, sum drho^2}, or the square roots of the two sums when
 // sqrt_l2.
-hipError_t launch_residual(int lat, int dtype, const void* src, bool swapped, const double* rho_ref,
+hipError_t launch_residual(int lat, int dtype, const void* src, int layout, const double* rho_ref,
                            const double* u_ref, const ChunkDesc* chunks, int nchunks, const BoxDesc* boxes,
                            long long nsites, double* partial, double* out, bool sqrt_l2, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);

@@ -32,20 +32,45 @@ __device__ __forceinline__ long long site_elem(long long local, int w, int Q)
     return r * Q * w + x;
 }
 
+// Element of population i of the site `local` of a single box (row tiles,
+// w = nx) when the state is in layout LAYOUT (StateLayout, internal.hpp):
+// natural: the site's own cell, tile row m(i); swapped: cell x + c_i, tile row
+// m(opp(i)); twisted: cell x + b_i (b_i the positive part of c_i), tile row
+// m(i) at even times and m(opp(i)) at odd times.
+template <class L, int LAYOUT, int I>
+__device__ __forceinline__ long long layout_elem(long long local, const BoxDesc& b)
+{
+    const long long r = local / b.nx;
+    const int x = int(local - r * b.nx);
+    const int y = int(r % b.ny);
+    const int z = int(r / b.ny);
+    const long long tile = (long long)L::Q * b.nx;
+    constexpr bool SW = (LAYOUT == kSwapped);
+    constexpr int ox = SW ? L::c[I][0] : twist_offset<L>(I, 0);
+    constexpr int oy = SW ? L::c[I][1] : twist_offset<L>(I, 1);
+    constexpr int oz = SW ? L::c[I][2] : twist_offset<L>(I, 2);
+    constexpr int m = (LAYOUT == kTwistEven) ? mem_row<L>(I) : mem_row<L>(opp(I));
+    const int xs = wrap_coord(x + ox, b.nx), ys = wrap_coord(y + oy, b.ny), zs = wrap_coord(z + oz, b.nz);
+    return ((long long)zs * b.ny + ys) * tile + (long long)m * b.nx + xs;
+}
+
 // Initialisation: f := f^eq_K(rho, u) (eq. hermite), evaluated in double and
-// rounded once to the storage type (set-up, not part of the step).
-template <class L, class S, int K>
+// rounded once to the storage type (set-up, not part of the step), written in
+// the natural layout or (single box) the twisted layout of an even time.
+template <class L, class S, int K, int LAYOUT>
 __global__ __launch_bounds__(256) void k_init(const double* __restrict__ rho, const double* __restrict__ u,
                                               S* __restrict__ dst, const ChunkDesc* __restrict__ chunks,
                                               const BoxDesc* __restrict__ boxes, long long nsites)
 {
     using ST = Store<S>;
+    static_assert(LAYOUT == kNatural || LAYOUT == kTwistEven, "init writes a layout of time 0");
     const ChunkDesc ch = chunks[blockIdx.x];
     const BoxDesc b = boxes[ch.box];
     S* base = dst + b.mem;
     for (int k = threadIdx.x; k < ch.count; k += blockDim.x) {
         const long long s = ch.start + k;
-        const long long e = site_elem(s - b.offset, b.w, L::Q);
+        const long long local = s - b.offset;
+        const long long e = site_elem(local, b.w, L::Q);
         const double ux = u[s];
         const double uy = u[nsites + s];
         const double uz = (L::D == 3) ? u[2 * nsites + s] : 0.0;
@@ -53,8 +78,8 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ rho, co
         equilibrium_scaled<L, K, double>(rho[s] - 1.0, ux, uy, uz, g);
         unroll<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            constexpr int m = mem_row<L>(i);
-            ST::put_d(base + e + (long long)m * b.w, g[i]);
+            if constexpr (LAYOUT == kNatural) ST::put_d(base + e + (long long)mem_row<L>(i) * b.w, g[i]);
+            else ST::put_d(base + layout_elem<L, LAYOUT, i>(local, b), g[i]);
         });
     }
 }
@@ -85,28 +110,19 @@ __device__ __forceinline__ void site_moments(const S* __restrict__ p, int w, dou
     j[2] /= double(L::S);
 }
 
-// The same for a box whose state the in-place step left in the swapped layout:
-// population i of site (x, y, z) sits at site (x, y, z) + c_i, tile row
-// m(opp(i)).  `local` is the site's index inside its box.  Single boxes only
-// (row tiles, w = nx).
-template <class L, class S>
-__device__ __forceinline__ void swapped_site_moments(const S* __restrict__ base, long long local, const BoxDesc& b,
-                                                     double& dsum, double (&j)[3])
+// The same for a single box whose state is in one of the in-place steps'
+// layouts (layout_elem).  `local` is the site's index inside its box.
+template <class L, class S, int LAYOUT>
+__device__ __forceinline__ void relaid_site_moments(const S* __restrict__ base, long long local, const BoxDesc& b,
+                                                    double& dsum, double (&j)[3])
 {
     using ST = Store<S>;
-    const long long r = local / b.nx;
-    const int x = int(local - r * b.nx);
-    const int y = int(r % b.ny);
-    const int z = int(r / b.ny);
-    const long long tile = (long long)L::Q * b.nx;
     dsum = 0.0;
     j[0] = j[1] = j[2] = 0.0;
     unroll<L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
-        constexpr int m = mem_row<L>(opp(i));
-        const int xs = wrap_coord(x + cx, b.nx), ys = wrap_coord(y + cy, b.ny), zs = wrap_coord(z + cz, b.nz);
-        const double gi = double(ST::get(base + ((long long)zs * b.ny + ys) * tile + (long long)m * b.nx + xs));
+        const double gi = double(ST::get(base + layout_elem<L, LAYOUT, i>(local, b)));
         dsum += gi;
         if constexpr (cx != 0) j[0] += double(cx) * gi;
         if constexpr (cy != 0) j[1] += double(cy) * gi;
@@ -118,15 +134,15 @@ __device__ __forceinline__ void swapped_site_moments(const S* __restrict__ base,
     j[2] /= double(L::S);
 }
 
-template <class L, class S, bool SWAPPED>
+template <class L, class S, int LAYOUT>
 __device__ __forceinline__ void stored_site_moments(const S* __restrict__ base, long long local, const BoxDesc& b,
                                                     double& dsum, double (&j)[3])
 {
-    if constexpr (SWAPPED) swapped_site_moments<L, S>(base, local, b, dsum, j);
+    if constexpr (LAYOUT != kNatural) relaid_site_moments<L, S, LAYOUT>(base, local, b, dsum, j);
     else site_moments<L, S>(base + site_elem(local, b.w, L::Q), b.w, dsum, j);
 }
 
-template <class L, class S, bool SWAPPED>
+template <class L, class S, int LAYOUT>
 __global__ __launch_bounds__(256) void k_moments(const S* __restrict__ src, double* __restrict__ rho,
                                                  double* __restrict__ u, const ChunkDesc* __restrict__ chunks,
                                                  const BoxDesc* __restrict__ boxes, long long nsites)
@@ -137,7 +153,7 @@ __global__ __launch_bounds__(256) void k_moments(const S* __restrict__ src, doub
     for (int k = threadIdx.x; k < ch.count; k += blockDim.x) {
         const long long s = ch.start + k;
         double d, j[3];
-        stored_site_moments<L, S, SWAPPED>(base, s - b.offset, b, d, j);
+        stored_site_moments<L, S, LAYOUT>(base, s - b.offset, b, d, j);
         const double r = 1.0 + d;
         rho[s] = r;
 #pragma unroll
@@ -172,7 +188,7 @@ __device__ __forceinline__ void block_tree(double (&acc)[NV], const bool (&is_ma
     for (int k = 0; k < NV; ++k) acc[k] = sh[k][0];
 }
 
-template <class L, class S, bool SWAPPED>
+template <class L, class S, int LAYOUT>
 __global__ __launch_bounds__(kRedBlock) void k_totals_partial(const S* __restrict__ src,
                                                               const ChunkDesc* __restrict__ chunks,
                                                               const BoxDesc* __restrict__ boxes,
@@ -184,7 +200,7 @@ __global__ __launch_bounds__(kRedBlock) void k_totals_partial(const S* __restric
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int k = threadIdx.x; k < ch.count; k += kRedBlock) {
         double d, j[3];
-        stored_site_moments<L, S, SWAPPED>(base, ch.start + k - b.offset, b, d, j);
+        stored_site_moments<L, S, LAYOUT>(base, ch.start + k - b.offset, b, d, j);
         acc[0] += d;
         acc[1] += j[0];
         acc[2] += j[1];
@@ -217,7 +233,7 @@ __global__ __launch_bounds__(kRedBlock) void k_totals_final(const double* __rest
         for (int k = 0; k < 4; ++k) out[b * 4 + k] = acc[k];
 }
 
-template <class L, class S, bool SWAPPED>
+template <class L, class S, int LAYOUT>
 __global__ __launch_bounds__(kRedBlock) void k_residual_partial(const S* __restrict__ src,
                                                                 const double* __restrict__ rho_ref,
                                                                 const double* __restrict__ u_ref,
@@ -232,7 +248,7 @@ __global__ __launch_bounds__(kRedBlock) void k_residual_partial(const S* __restr
     for (int k = threadIdx.x; k < ch.count; k += kRedBlock) {
         const long long s = ch.start + k;
         double d, j[3];
-        stored_site_moments<L, S, SWAPPED>(base, s - b.offset, b, d, j);
+        stored_site_moments<L, S, LAYOUT>(base, s - b.offset, b, d, j);
         const double r = 1.0 + d;
 #pragma unroll
         for (int a = 0; a < L::D; ++a) {
@@ -283,66 +299,81 @@ __global__ __launch_bounds__(256) void k_copy(const u32x4* __restrict__ src, u32
     if (k < n) __builtin_nontemporal_store(__builtin_nontemporal_load(src + k), dst + k);
 }
 
-hipError_t launch_init(int lat, int dtype, int K, const double* rho, const double* u, void* dst,
+// Calls f(integral_constant layout) for a runtime StateLayout.
+template <class F>
+static hipError_t by_layout(int layout, F&& f)
+{
+    switch (layout) {
+    case kNatural: return f(ic<kNatural>{});
+    case kSwapped: return f(ic<kSwapped>{});
+    case kTwistEven: return f(ic<kTwistEven>{});
+    case kTwistOdd: return f(ic<kTwistOdd>{});
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_init(int lat, int dtype, int K, int layout, const double* rho, const double* u, void* dst,
                        const ChunkDesc* chunks, int nchunks, const BoxDesc* boxes, long long nsites, hipStream_t s)
 {
+    if (layout != kNatural && layout != kTwistEven) return hipErrorInvalidValue;
     return dispatch(lat, dtype, K, [&](auto Lt, auto* Sp, auto Kc) -> hipError_t {
         using L = decltype(Lt);
         using S = std::remove_pointer_t<decltype(Sp)>;
         constexpr int KK = decltype(Kc)::value;
-        k_init<L, S, KK><<<nchunks, 256, 0, s>>>(rho, u, static_cast<S*>(dst), chunks, boxes, nsites);
+        if (layout == kTwistEven)
+            k_init<L, S, KK, kTwistEven><<<nchunks, 256, 0, s>>>(rho, u, static_cast<S*>(dst), chunks, boxes, nsites);
+        else
+            k_init<L, S, KK, kNatural><<<nchunks, 256, 0, s>>>(rho, u, static_cast<S*>(dst), chunks, boxes, nsites);
         return hipGetLastError();
     });
 }
 
-hipError_t launch_moments(int lat, int dtype, const void* src, bool swapped, double* rho, double* u,
+hipError_t launch_moments(int lat, int dtype, const void* src, int layout, double* rho, double* u,
                           const ChunkDesc* chunks, int nchunks, const BoxDesc* boxes, long long nsites, hipStream_t s)
 {
     return dispatch_ld(lat, dtype, [&](auto Lt, auto* Sp, auto) -> hipError_t {
         using L = decltype(Lt);
         using S = std::remove_pointer_t<decltype(Sp)>;
-        if (swapped)
-            k_moments<L, S, true><<<nchunks, 256, 0, s>>>(static_cast<const S*>(src), rho, u, chunks, boxes, nsites);
-        else
-            k_moments<L, S, false><<<nchunks, 256, 0, s>>>(static_cast<const S*>(src), rho, u, chunks, boxes, nsites);
-        return hipGetLastError();
+        return by_layout(layout, [&](auto Lay) -> hipError_t {
+            constexpr int LAY = decltype(Lay)::value;
+            k_moments<L, S, LAY><<<nchunks, 256, 0, s>>>(static_cast<const S*>(src), rho, u, chunks, boxes, nsites);
+            return hipGetLastError();
+        });
     });
 }
 
-hipError_t launch_totals(int lat, int dtype, const void* src, bool swapped, const ChunkDesc* chunks, int nchunks,
+hipError_t launch_totals(int lat, int dtype, const void* src, int layout, const ChunkDesc* chunks, int nchunks,
                          const int* box_chunk_begin, int nbox, const BoxDesc* boxes, double* partial, double* out,
                          hipStream_t s)
 {
     return dispatch_ld(lat, dtype, [&](auto Lt, auto* Sp, auto) -> hipError_t {
         using L = decltype(Lt);
         using S = std::remove_pointer_t<decltype(Sp)>;
-        if (swapped)
-            k_totals_partial<L, S, true><<<nchunks, kRedBlock, 0, s>>>(static_cast<const S*>(src), chunks, boxes,
-                                                                       partial);
-        else
-            k_totals_partial<L, S, false><<<nchunks, kRedBlock, 0, s>>>(static_cast<const S*>(src), chunks, boxes,
-                                                                        partial);
-        hipError_t e = hipGetLastError();
+        hipError_t e = by_layout(layout, [&](auto Lay) -> hipError_t {
+            constexpr int LAY = decltype(Lay)::value;
+            k_totals_partial<L, S, LAY><<<nchunks, kRedBlock, 0, s>>>(static_cast<const S*>(src), chunks, boxes,
+                                                                      partial);
+            return hipGetLastError();
+        });
         if (e != hipSuccess) return e;
         k_totals_final<<<nbox, kRedBlock, 0, s>>>(partial, box_chunk_begin, out);
         return hipGetLastError();
     });
 }
 
-hipError_t launch_residual(int lat, int dtype, const void* src, bool swapped, const double* rho_ref,
+hipError_t launch_residual(int lat, int dtype, const void* src, int layout, const double* rho_ref,
                            const double* u_ref, const ChunkDesc* chunks, int nchunks, const BoxDesc* boxes,
                            long long nsites, double* partial, double* out, bool sqrt_l2, hipStream_t s)
 {
     return dispatch_ld(lat, dtype, [&](auto Lt, auto* Sp, auto) -> hipError_t {
         using L = decltype(Lt);
         using S = std::remove_pointer_t<decltype(Sp)>;
-        if (swapped)
-            k_residual_partial<L, S, true><<<nchunks, kRedBlock, 0, s>>>(static_cast<const S*>(src), rho_ref, u_ref,
-                                                                         chunks, boxes, nsites, partial);
-        else
-            k_residual_partial<L, S, false><<<nchunks, kRedBlock, 0, s>>>(static_cast<const S*>(src), rho_ref, u_ref,
-                                                                          chunks, boxes, nsites, partial);
-        hipError_t e = hipGetLastError();
+        hipError_t e = by_layout(layout, [&](auto Lay) -> hipError_t {
+            constexpr int LAY = decltype(Lay)::value;
+            k_residual_partial<L, S, LAY><<<nchunks, kRedBlock, 0, s>>>(static_cast<const S*>(src), rho_ref, u_ref,
+                                                                        chunks, boxes, nsites, partial);
+            return hipGetLastError();
+        });
         if (e != hipSuccess) return e;
         k_residual_final<<<1, kRedBlock, 0, s>>>(partial, nchunks, out, sqrt_l2 ? 1 : 0);
         return hipGetLastError();
@@ -358,46 +389,55 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s)
     return hipGetLastError();
 }
 
-// Swapped layout of the in-place step -> natural layout, into another buffer:
-// population j of site x is read from site x + c_j, tile row m(opp(j)).  A
-// pure permutation of stored values (bit-exact), single box.
-template <class L, class S>
-__global__ __launch_bounds__(256) void k_unswap(const S* __restrict__ src, S* __restrict__ dst, StepGeom geo)
+// Layout conversions of a single box's state between the natural layout and
+// one of the in-place steps' layouts (layout_elem), into another buffer: a
+// pure permutation of stored values (bit-exact).  TO_NATURAL: population i of
+// site x is read at its element in LAYOUT and written to its natural element;
+// otherwise the other way round.  One thread per site.
+template <class L, class S, int LAYOUT, bool TO_NATURAL>
+__global__ __launch_bounds__(256) void k_relayout(const S* __restrict__ src, S* __restrict__ dst, BoxDesc b)
 {
-    constexpr int RR = L::R;
     const int y = blockIdx.y;
     const int z = blockIdx.z;
     const int x = int(blockIdx.x) * int(blockDim.x) + int(threadIdx.x);
-    if (x >= geo.nx) return;
-    const long long tile = (long long)L::Q * geo.nx;
-    int xw[2 * RR + 1], yw[2 * RR + 1], zw[2 * RR + 1];
-#pragma unroll
-    for (int k = 0; k <= 2 * RR; ++k) {
-        xw[k] = wrap_coord(x + k - RR, geo.nx);
-        yw[k] = wrap_coord(y + k - RR, geo.ny);
-        zw[k] = wrap_coord(z + k - RR, geo.nz);
-    }
-    S* q = dst + (long long)(z * geo.ny + y) * tile;
-    unroll<L::Q>([&](auto J) {
-        constexpr int j = decltype(J)::value;
-        constexpr int cx = L::c[j][0], cy = L::c[j][1], cz = L::c[j][2];
-        const int row = zw[RR + cz] * geo.ny + yw[RR + cy];
-        constexpr int m_src = mem_row<L>(opp(j));
-        constexpr int m_dst = mem_row<L>(j);
-        const S* p = src + row * tile + (long long)m_src * geo.nx;
-        q[(long long)m_dst * geo.nx + x] = p[xw[RR + cx]];
+    if (x >= b.nx) return;
+    const long long local = ((long long)z * b.ny + y) * b.nx + x;
+    const long long nat = site_elem(local, b.nx, L::Q);
+    unroll<L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        const long long e = layout_elem<L, LAYOUT, i>(local, b);
+        const long long n = nat + (long long)mem_row<L>(i) * b.nx;
+        if constexpr (TO_NATURAL) dst[n] = src[e];
+        else dst[e] = src[n];
     });
 }
 
-hipError_t launch_unswap(int lat, int dtype, const void* src, void* dst, const StepGeom& geo, int block,
-                         hipStream_t s)
+hipError_t launch_relayout(int lat, int dtype, int layout, bool to_natural, const void* src, void* dst,
+                           const StepGeom& geo, int block, hipStream_t s)
 {
+    if (layout == kNatural) return hipErrorInvalidValue;
+    BoxDesc b{};
+    b.nx = geo.nx;
+    b.ny = geo.ny;
+    b.nz = geo.nz;
+    b.w = geo.nx;
+    const dim3 grid(unsigned(geo.xblocks), unsigned(geo.ny), unsigned(geo.nz));
     return dispatch_ld(lat, dtype, [&](auto Lt, auto* Sp, auto) -> hipError_t {
         using L = decltype(Lt);
         using S = std::remove_pointer_t<decltype(Sp)>;
-        k_unswap<L, S><<<dim3(unsigned(geo.xblocks), unsigned(geo.ny), unsigned(geo.nz)), block, 0, s>>>(
-            static_cast<const S*>(src), static_cast<S*>(dst), geo);
-        return hipGetLastError();
+        return by_layout(layout, [&](auto Lay) -> hipError_t {
+            constexpr int LAY = decltype(Lay)::value;
+            if constexpr (LAY != kNatural) {
+                if (to_natural)
+                    k_relayout<L, S, LAY, true><<<grid, block, 0, s>>>(static_cast<const S*>(src),
+                                                                       static_cast<S*>(dst), b);
+                else
+                    k_relayout<L, S, LAY, false><<<grid, block, 0, s>>>(static_cast<const S*>(src),
+                                                                        static_cast<S*>(dst), b);
+                return hipGetLastError();
+            }
+            return hipErrorInvalidValue;
+        });
     });
 }
 
@@ -453,6 +493,16 @@ hipError_t launch_step_ip(int lat, int dtype, int K, int kind, void* buf, bool f
         using L = decltype(Lt);
         using S = std::remove_pointer_t<decltype(Sp)>;
         return launch_step_ip_l<L, S>(K, kind, buf, from_natural, geo, omega, theta, block, s);
+    });
+}
+
+hipError_t launch_step_tw(int lat, int dtype, int K, int kind, void* buf, bool even, const StepGeom& geo,
+                          double omega, double theta, int block, hipStream_t s)
+{
+    return by_pair(lat, dtype, [&](auto Lt, auto* Sp) {
+        using L = decltype(Lt);
+        using S = std::remove_pointer_t<decltype(Sp)>;
+        return launch_step_tw_l<L, S>(K, kind, buf, even, geo, omega, theta, block, s);
     });
 }
 

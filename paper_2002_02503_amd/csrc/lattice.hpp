@@ -174,6 +174,16 @@ static_assert(integer_weights_consistent<D3Q39>(), "D3Q39 weight quantum");
 // Index of the velocity opposite to c_i (rest first, then pairs (2k-1, 2k)).
 constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
 
+// Twisted layouts of the in-place "twist" step (step.hpp, k_step_tw): the
+// populations of site x are kept at the cells x + b_i, b_i the positive part
+// of c_i, component by component.  Population i of site x is in tile row m(i)
+// at even times and in tile row m(opp(i)) at odd times.
+template <class L>
+constexpr int twist_offset(int i, int a)
+{
+    return L::c[i][a] > 0 ? L::c[i][a] : 0;
+}
+
 // Memory order of the populations inside a row tile: sorted by (c_z, c_y, c_x),
 // so the populations a step pulls from one neighbouring row tile are adjacent
 // rows of that tile.  mem_row(i) is the tile row of population i, mem_pop(m)

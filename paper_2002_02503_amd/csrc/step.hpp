@@ -1,6 +1,7 @@
 // The fused pull-stream + collide step on a single box: one site per thread
-// (k_step) or V sites per lane (k_step_vec), templated on lattice, storage
-// type, Hermite order and collision kind.  Included by the per-lattice
+// (k_step, k_step_pair, and the in-place forms k_step_ip and k_step_tw) or V
+// sites per lane (k_step_vec), templated on lattice, storage type, Hermite
+// order and collision kind.  Included by the per-lattice
 // translation units, which instantiate the launchers for one lattice.
 #pragma once
 
@@ -197,6 +198,70 @@ __global__ __launch_bounds__(256) void k_step_ip(S* __restrict__ buf, StepGeom g
     }
 }
 
+// ---------------------------------------------------------------------------
+// Fused step, single box, in place with the twisted layouts ("esoteric twist").
+// The populations of site x are kept at the cells x + b_i, b_i the positive
+// part of c_i component by component (lattice.hpp, twist_offset); population
+// i is in tile row m(i) at even times and m(opp(i)) at odd times.  Site x
+// finds its incoming population i (f'_i of site x - c_i) at the cell
+// x - c_i + b_i = x + b_opp(i): tile row m(i) at an even time, m(opp(i)) at
+// an odd one.  After the collision it writes its population opp(i) back into
+// that same element, which is where that population belongs at the next
+// time.  So every step reads and writes each element once, by one thread,
+// and every step of both parities touches only the cells x + b: for D3Q19
+// four row tiles (own, +y, +z, +y+z) and x offsets 0 and +1, for D3Q39 nine
+// row tiles and x offsets 0..3.  The per-site arithmetic is that of k_step
+// (the same bits).
+// ---------------------------------------------------------------------------
+
+template <class L, class S, int K, int KIND, bool EVEN>
+__global__ __launch_bounds__(256) void k_step_tw(S* __restrict__ buf, StepGeom geo, typename Store<S>::R omega,
+                                                 typename Store<S>::R theta)
+{
+    using ST = Store<S>;
+    using R = typename ST::R;
+    constexpr bool PROJ = !std::is_same<R, double>::value;
+    constexpr int RR = L::R;
+
+    const int y = blockIdx.y;
+    const int z = blockIdx.z;
+    const int x = int(blockIdx.x) * int(blockDim.x) + int(threadIdx.x);
+    if (x >= geo.nx) return;
+    const long long tile = (long long)L::Q * geo.nx;
+
+    int xw[RR + 1], yw[RR + 1], zw[RR + 1];
+#pragma unroll
+    for (int k = 0; k <= RR; ++k) {
+        xw[k] = wrap_coord(x + k, geo.nx);
+        yw[k] = wrap_coord(y + k, geo.ny);
+        zw[k] = wrap_coord(z + k, geo.nz);
+    }
+    // tile row m holds, for this site, population pop_in_row(m) at the cell
+    // x + b_opp(pop_in_row(m))
+    auto elem = [&](auto M) -> S* {
+        constexpr int m = decltype(M)::value;
+        constexpr int i = EVEN ? mem_pop<L>(m) : opp(mem_pop<L>(m));
+        constexpr int io = opp(i);
+        const int row = zw[twist_offset<L>(io, 2)] * geo.ny + yw[twist_offset<L>(io, 1)];
+        return at32(buf + row * tile + (long long)m * geo.nx, unsigned(xw[twist_offset<L>(io, 0)]));
+    };
+    R g[L::Q];
+    unroll<L::Q>([&](auto M) {  // in tile-row order
+        constexpr int i = EVEN ? mem_pop<L>(decltype(M)::value) : opp(mem_pop<L>(decltype(M)::value));
+        // elements at the site's own x belong to this wavefront alone
+        if constexpr (twist_offset<L>(opp(i), 0) == 0) g[i] = ST::get_nt(elem(M));
+        else g[i] = ST::get(elem(M));
+    });
+    collide_site<L, K, KIND, PROJ, R>(g, omega, theta);
+    unroll<L::Q>([&](auto M) {
+        constexpr int i = EVEN ? mem_pop<L>(decltype(M)::value) : opp(mem_pop<L>(decltype(M)::value));
+        constexpr int io = opp(i);
+        const R v = g[io];
+        if constexpr (twist_offset<L>(io, 0) == 0) ST::put_nt(elem(M), v);
+        else ST::put(elem(M), v);
+    });
+}
+
 template <class L, class S, int K, int KIND>
 __global__ __launch_bounds__(256) void k_step_vec(const S* __restrict__ src, S* __restrict__ dst, VecGeom geo,
                                                   typename Store<S>::R omega, typename Store<S>::R theta)
@@ -307,6 +372,23 @@ hipError_t launch_step_ip_l(int K, int kind, void* buf, bool from_natural, const
             k_step_ip<L, S, KK, KD, true><<<grid, block, 0, s>>>(static_cast<S*>(buf), geo, R(omega), R(theta));
         else
             k_step_ip<L, S, KK, KD, false><<<grid, block, 0, s>>>(static_cast<S*>(buf), geo, R(omega), R(theta));
+        return hipGetLastError();
+    });
+}
+
+template <class L, class S>
+hipError_t launch_step_tw_l(int K, int kind, void* buf, bool even, const StepGeom& geo, double omega, double theta,
+                            int block, hipStream_t s)
+{
+    return dispatch_pair<L, S>(K, kind, [&](auto, auto*, auto Kc, auto Kind) -> hipError_t {
+        using R = typename Store<S>::R;
+        constexpr int KK = decltype(Kc)::value;
+        constexpr int KD = decltype(Kind)::value;
+        const dim3 grid(unsigned(geo.xblocks), unsigned(geo.ny), unsigned(geo.nz));
+        if (even)
+            k_step_tw<L, S, KK, KD, true><<<grid, block, 0, s>>>(static_cast<S*>(buf), geo, R(omega), R(theta));
+        else
+            k_step_tw<L, S, KK, KD, false><<<grid, block, 0, s>>>(static_cast<S*>(buf), geo, R(omega), R(theta));
         return hipGetLastError();
     });
 }

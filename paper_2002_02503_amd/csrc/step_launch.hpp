@@ -25,6 +25,12 @@ template <class L, class S>
 hipError_t launch_step_ip_l(int K, int kind, void* buf, bool from_natural, const StepGeom& geo, double omega,
                             double theta, int block, hipStream_t s);
 
+// Single box, in place on the twisted layouts: from an even time (even) or
+// an odd one (see k_step_tw).
+template <class L, class S>
+hipError_t launch_step_tw_l(int K, int kind, void* buf, bool even, const StepGeom& geo, double omega, double theta,
+                            int block, hipStream_t s);
+
 // Sites per lane of the row-wave form (0: none for this pair).
 template <class L, class S>
 int vec_sites_l();
@@ -44,6 +50,8 @@ hipError_t launch_step_batch_l(int K, int kind, const void* src, void* dst, cons
     EXT template hipError_t launch_step_l<L, S>(int, int, const void*, void*, const StepGeom&, double, double,  \
                                                 int, bool, hipStream_t);                                       \
     EXT template hipError_t launch_step_ip_l<L, S>(int, int, void*, bool, const StepGeom&, double, double, int, \
+                                                   hipStream_t);                                               \
+    EXT template hipError_t launch_step_tw_l<L, S>(int, int, void*, bool, const StepGeom&, double, double, int, \
                                                    hipStream_t);                                               \
     EXT template int vec_sites_l<L, S>();                                                                      \
     EXT template hipError_t launch_step_vec_l<L, S>(int, int, const void*, void*, const VecGeom&, double,      \

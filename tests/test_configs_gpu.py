@@ -145,7 +145,7 @@ def test_d3q39_shear_wave_192_fp32():
     assert gal["D3Q39"] < gal["D3Q19"]
 
 
-@pytest.mark.parametrize("kernel", ["scalar", "in_place"])
+@pytest.mark.parametrize("kernel", ["scalar", "in_place", "twist"])
 def test_d3q39_k5_shear_wave_192_fp32(kernel):
     """D3Q39 at K = 5 (the benchmark's variant), 192^3, FP32, shear wave on
     U = (0.2, 0, 0), 200 steps, in the launch the tuner picks for it (the
@@ -197,7 +197,7 @@ VARIANT_CASES = [
 ]
 
 
-@pytest.mark.parametrize("kernel", ["scalar", "in_place"])
+@pytest.mark.parametrize("kernel", ["scalar", "in_place", "twist"])
 @pytest.mark.parametrize("lattice,lib_kw,ora_kw", VARIANT_CASES)
 def test_turbulence_256_sampled_parity_variants(turbulence_256, lattice, lib_kw, ora_kw, kernel):
     """The benchmark's other collision kinds and D3Q15 on the full 256^3
@@ -225,8 +225,8 @@ def turbulence_256_samples(turbulence_256):
     return pts, r_ref, u_ref
 
 
-@pytest.mark.parametrize("kernel", ["in_place", "two_row"])
-@pytest.mark.parametrize("dtype", ["fp32", "bf16"])
+@pytest.mark.parametrize("kernel", ["in_place", "two_row", "twist"])
+@pytest.mark.parametrize("dtype", ["fp32", "fp16", "bf16"])
 def test_turbulence_256_sampled_parity_other_kernels(turbulence_256, turbulence_256_samples, kernel, dtype):
     """The same full-size check for the kernel forms the tuner may pick for the
     benchmark (after 3 steps the in-place state is in its swapped layout)."""

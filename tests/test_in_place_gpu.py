@@ -1,7 +1,8 @@
-"""The in-place step (one buffer, two alternating layouts of the state) against
-the two-buffer step: the same bits after any number of steps, whatever the
-graph chunking; readers (moments, totals, residual, checkpoints) see the
-natural layout at odd and even times; and parity with the oracle."""
+"""The in-place steps (one buffer, two alternating layouts of the state: the
+swapped form k_step_ip and the twisted form k_step_tw) against the two-buffer
+step: the same bits after any number of steps, whatever the graph chunking;
+readers (moments, totals, residual, checkpoints) see the natural layout at
+odd and even times; and parity with the oracle."""
 import numpy as np
 import pytest
 
@@ -29,59 +30,67 @@ CASES = [
 ]
 
 
+IN_PLACE = ["in_place", "twist"]
+
+
+@pytest.mark.parametrize("kernel", IN_PLACE)
 @pytest.mark.parametrize("lattice,dims,dtype,kw", CASES)
 @pytest.mark.parametrize("steps", [1, 2, 7, 40])
-def test_in_place_equals_two_buffer_step(lattice, dims, dtype, kw, steps):
+def test_in_place_equals_two_buffer_step(lattice, dims, dtype, kw, steps, kernel):
     D = 2 if lattice == "D2Q9" else 3
     rho, u = _fields(D, dims, seed=steps + sum(dims))
-    a = run_gpu(lattice, dims, 0.6, dtype, rho, u, steps, kernel="in_place", **kw)
+    a = run_gpu(lattice, dims, 0.6, dtype, rho, u, steps, kernel=kernel, **kw)
     b = run_gpu(lattice, dims, 0.6, dtype, rho, u, steps, kernel="scalar", **kw)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
+@pytest.mark.parametrize("kernel", IN_PLACE)
 @pytest.mark.parametrize("chunk", [1, 3, 32])
-def test_in_place_graph_chunks(chunk):
+def test_in_place_graph_chunks(chunk, kernel):
     """Odd and even graph chunks alternate the layout inside a captured graph."""
     dims = (96, 5, 6)
     rho, u = _fields(3, dims, seed=chunk)
-    a = run_gpu("D3Q19", dims, 0.57, "fp32", rho, u, 77, kernel="in_place", graph_chunk=chunk)
+    a = run_gpu("D3Q19", dims, 0.57, "fp32", rho, u, 77, kernel=kernel, graph_chunk=chunk)
     b = run_gpu("D3Q19", dims, 0.57, "fp32", rho, u, 77, kernel="scalar")
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
+@pytest.mark.parametrize("kernel", IN_PLACE)
 @pytest.mark.parametrize("lattice,dims", [("D3Q19", (1, 2, 3)), ("D3Q19", (2, 2, 2)), ("D3Q39", (1, 1, 1)),
                                           ("D3Q39", (2, 1, 5)), ("D3Q39", (5, 3, 2)), ("D2Q9", (2, 3, 1))])
-def test_in_place_degenerate_boxes(lattice, dims):
+def test_in_place_degenerate_boxes(lattice, dims, kernel):
     """Boxes shorter than the velocities: every element is still read and
     written by exactly one thread."""
     D = 2 if lattice == "D2Q9" else 3
     rho, u = _fields(D, dims, seed=3)
     r_ref, u_ref = run_oracle(lattice, dims, 0.7, rho, u, 25)
     for dtype in ["fp64", "fp32"]:
-        r, uu = run_gpu(lattice, dims, 0.7, dtype, rho, u, 25, kernel="in_place")
+        r, uu = run_gpu(lattice, dims, 0.7, dtype, rho, u, 25, kernel=kernel)
         assert rel_u(uu, u_ref) < BOUND[dtype] and rel_rho(r, r_ref) < BOUND[dtype]
         r2, u2 = run_gpu(lattice, dims, 0.7, dtype, rho, u, 25, kernel="scalar")
         assert np.array_equal(r, r2) and np.array_equal(uu, u2)
 
 
-def test_in_place_matches_oracle():
+@pytest.mark.parametrize("kernel", IN_PLACE)
+def test_in_place_matches_oracle(kernel):
     dims = (200, 6, 5)
     rho, u = _fields(3, dims, seed=11)
     r_ref, u_ref = run_oracle("D3Q19", dims, 0.55, rho, u, 31, mode="closed")
     for dtype in ["fp64", "fp32", "fp16", "bf16"]:
-        r, uu = run_gpu("D3Q19", dims, 0.55, dtype, rho, u, 31, kernel="in_place")
+        r, uu = run_gpu("D3Q19", dims, 0.55, dtype, rho, u, 31, kernel=kernel)
         assert rel_u(uu, u_ref) < BOUND[dtype] and rel_rho(r, r_ref) < BOUND[dtype]
 
 
-def test_readers_at_odd_and_even_times():
+@pytest.mark.parametrize("kernel", IN_PLACE)
+def test_readers_at_odd_and_even_times(kernel):
     """Moments, totals, residual and checkpoints after odd and even step
     counts equal those of the two-buffer step, and a checkpoint taken at an odd
-    time resumes bit for bit in either kernel."""
+    time resumes bit for bit in every kernel."""
     from paper_2002_02503_amd import lbm
 
     dims = (64, 9, 7)
     rho, u = _fields(3, dims, seed=5)
-    with lbm.Simulation("D3Q19", dims, 0.6, dtype="fp32", kernel="in_place") as ip, \
+    with lbm.Simulation("D3Q19", dims, 0.6, dtype="fp32", kernel=kernel) as ip, \
             lbm.Simulation("D3Q19", dims, 0.6, dtype="fp32", kernel="scalar") as sc:
         ip.init(rho, u)
         sc.init(rho, u)
@@ -100,8 +109,8 @@ def test_readers_at_odd_and_even_times():
         ip.step(5)
         sc.step(5)
         ref = sc.moments()
-        for kernel in ["in_place", "scalar"]:
-            with lbm.Simulation("D3Q19", dims, 0.6, dtype="fp32", kernel=kernel) as other:
+        for other_kernel in ["in_place", "twist", "scalar"]:
+            with lbm.Simulation("D3Q19", dims, 0.6, dtype="fp32", kernel=other_kernel) as other:
                 other.set_state(ck)
                 assert other.t == 7
                 other.step(5)
@@ -109,33 +118,41 @@ def test_readers_at_odd_and_even_times():
                 assert np.array_equal(r, ref[0]) and np.array_equal(uu, ref[1])
 
 
-def test_in_place_is_rejected_for_batches():
+@pytest.mark.parametrize("kernel", IN_PLACE)
+def test_in_place_is_rejected_for_batches(kernel):
     from paper_2002_02503_amd import lbm
 
     with pytest.raises(lbm.LBMError) as e:
-        lbm.Simulation("D3Q19", [(8, 8, 8), (9, 9, 9)], [0.6, 0.7], kernel="in_place")
+        lbm.Simulation("D3Q19", [(8, 8, 8), (9, 9, 9)], [0.6, 0.7], kernel=kernel)
     assert e.value.name == "LBM_EINVAL"
 
 
-def test_tuning_across_layouts_keeps_the_state():
-    """The tuner switches between the in-place and two-buffer kernels with the
-    state at an odd time; afterwards the run continues bit for bit."""
+@pytest.mark.parametrize("kernel", IN_PLACE + ["scalar"])
+@pytest.mark.parametrize("t0", [3, 4])
+def test_tuning_across_layouts_keeps_the_state(kernel, t0):
+    """The tuner switches between the in-place, twisted and two-buffer
+    kernels with the state at an odd or even time; afterwards the run
+    continues bit for bit, whichever kernel it chose."""
     from paper_2002_02503_amd import lbm
 
     dims = (128, 6, 5)
     rho, u = _fields(3, dims, seed=8)
-    ref = run_gpu("D3Q19", dims, 0.6, "fp32", rho, u, 13, kernel="scalar")
-    with lbm.Simulation("D3Q19", dims, 0.6, dtype="fp32", kernel="in_place") as sim:
-        sim.init(rho, u).step(3)
+    ref = run_gpu("D3Q19", dims, 0.6, "fp32", rho, u, t0 + 10, kernel="scalar")
+    with lbm.Simulation("D3Q19", dims, 0.6, dtype="fp32", kernel=kernel) as sim:
+        sim.init(rho, u).step(t0)
         sim.tune(steps=4)
-        assert sim.t == 3
+        assert sim.t == t0
+        r0, u0 = sim.moments()
         sim.step(10)
         r, uu = sim.moments()
+    mid = run_gpu("D3Q19", dims, 0.6, "fp32", rho, u, t0, kernel="scalar")
+    assert np.array_equal(r0, mid[0]) and np.array_equal(u0, mid[1])
     assert np.array_equal(r, ref[0]) and np.array_equal(uu, ref[1])
 
 
-def test_in_place_holds_one_buffer():
-    """With library-owned memory the in-place step allocates one population
+@pytest.mark.parametrize("kernel", IN_PLACE)
+def test_in_place_holds_one_buffer(kernel):
+    """With library-owned memory the in-place steps allocate one population
     buffer; reading at odd times (moments, totals, residual, checkpoint) needs
     no second one, and the results equal the two-buffer step's."""
     import torch
@@ -145,7 +162,7 @@ def test_in_place_holds_one_buffer():
     dims = (128, 128, 64)  # 128^2 * 64 * 19 * 4 B = 80 MiB per buffer
     rho, u = _fields(3, dims, seed=12, amp=0.03)
     ref = run_gpu("D3Q19", dims, 0.6, "fp32", rho, u, 9, kernel="scalar")
-    with lbm.Simulation("D3Q19", dims, 0.6, dtype="fp32", kernel="in_place", torch_memory=False) as sim:
+    with lbm.Simulation("D3Q19", dims, 0.6, dtype="fp32", kernel=kernel, torch_memory=False) as sim:
         nbytes = sim.info()["state_bytes"]
         torch.cuda.synchronize()
         free0 = torch.cuda.mem_get_info()[0]
@@ -155,7 +172,7 @@ def test_in_place_holds_one_buffer():
         ck = sim.get_state()
         torch.cuda.synchronize()
         used = free0 - torch.cuda.mem_get_info()[0]
-        print(f"in-place: {used / 2**20:.1f} MiB allocated for a {nbytes / 2**20:.1f} MiB state", flush=True)
+        print(f"{kernel}: {used / 2**20:.1f} MiB allocated for a {nbytes / 2**20:.1f} MiB state", flush=True)
         assert used < 1.5 * nbytes
     assert np.array_equal(r, ref[0]) and np.array_equal(uu, ref[1])
     with lbm.Simulation("D3Q19", dims, 0.6, dtype="fp32", kernel="scalar") as other:
@@ -202,20 +219,22 @@ def test_switching_kernels_mid_run_keeps_the_bits():
 
     dims = (64, 6, 5)
     rho, u = _fields(3, dims, seed=21)
-    ref = run_gpu("D3Q19", dims, 0.6, "fp32", rho, u, 12, kernel="scalar")
+    ref = run_gpu("D3Q19", dims, 0.6, "fp32", rho, u, 19, kernel="scalar")
     with lbm.Simulation("D3Q19", dims, 0.6, dtype="fp32", kernel="in_place", torch_memory=False) as sim:
         sim.init(rho, u).step(3)
-        for kernel in ["scalar", "in_place", "two_row", "in_place"]:
+        for kernel, n in [("scalar", 2), ("twist", 3), ("in_place", 2), ("twist", 2), ("two_row", 3), ("twist", 1),
+                          ("twist", 2), ("in_place", 1)]:
             assert lbm.STATUS[sim.lib.lbm_set_kernel(sim.h, lbm.KERNELS[kernel])] == "LBM_OK"
-            sim.step(2 if kernel != "two_row" else 3)
-        assert sim.t == 12
+            sim.step(n)
+        assert sim.t == 19
         r, uu = sim.moments()
     assert np.array_equal(r, ref[0]) and np.array_equal(uu, ref[1])
 
 
+@pytest.mark.parametrize("kernel", IN_PLACE)
 @pytest.mark.parametrize("lattice,dims", [("D3Q39", (40, 6, 5)), ("D2Q9", (50, 7, 1)), ("D3Q15", (33, 5, 4)),
                                           ("D3Q39", (2, 1, 5))])
-def test_odd_time_checkpoint_every_lattice(lattice, dims):
+def test_odd_time_checkpoint_every_lattice(lattice, dims, kernel):
     """A checkpoint taken after an odd number of in-place steps (the state is
     then swapped, and lbm_get_state rearranges it on the host) equals the
     two-buffer step's bytes, and resumes bit for bit in either kernel."""
@@ -223,7 +242,7 @@ def test_odd_time_checkpoint_every_lattice(lattice, dims):
 
     D = 2 if lattice == "D2Q9" else 3
     rho, u = _fields(D, dims, seed=31)
-    with lbm.Simulation(lattice, dims, 0.6, dtype="fp32", kernel="in_place") as ip, \
+    with lbm.Simulation(lattice, dims, 0.6, dtype="fp32", kernel=kernel) as ip, \
             lbm.Simulation(lattice, dims, 0.6, dtype="fp32", kernel="scalar") as sc:
         ip.init(rho, u).step(3)
         sc.init(rho, u).step(3)
@@ -231,9 +250,9 @@ def test_odd_time_checkpoint_every_lattice(lattice, dims):
         assert np.array_equal(ck, sc.get_state())
         sc.step(4)
         ref = sc.moments()
-    for kernel in ["in_place", "scalar"]:
-        with lbm.Simulation(lattice, dims, 0.6, dtype="fp32", kernel=kernel) as other:
+    for other_kernel in IN_PLACE + ["scalar"]:
+        with lbm.Simulation(lattice, dims, 0.6, dtype="fp32", kernel=other_kernel) as other:
             other.set_state(ck)
             other.step(4)
             r, uu = other.moments()
-        assert np.array_equal(r, ref[0]) and np.array_equal(uu, ref[1]), kernel
+        assert np.array_equal(r, ref[0]) and np.array_equal(uu, ref[1]), other_kernel
