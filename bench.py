@@ -6,9 +6,21 @@ turbulence from a seeded random-phase field (k0 = 4, u_rms = 0.04), FP32
 storage; FP16 and BF16 storage of the deviations, the batched form (256 boxes)
 and D3Q39 (192^3) are reported beside it.  A "step" is one application of the
 lattice Boltzmann equation to every site.  Inputs are resident in HBM before
-the timed region; the timed region is K steps issued as captured graphs,
-bracketed by device synchronisation, timed with HIP events on the stream the
-kernels run on.
+the timed region.  Each measurement sets the handle's graph chunk to
+min(K, 4096) and builds its step graphs beforehand, so the K timed steps are
+one captured-graph launch (K <= 4096); the W warm-up steps before them, fewer
+than one chunk, are direct launches.  The timed region is bracketed by device
+synchronisation and timed with HIP events on the stream the kernels run on.
+Every measurement records its graph chunk and how many graph and direct
+launches its timed steps took.
+
+Error statements (errors, and "error" in each variant) compare the GPU's
+fields with the FP64 oracle's on the same seeded inputs, on the full box where
+the oracle can run it in the time budget, else on exact reductions of the flow
+(x-only shear waves as nx x 1 x 1 runs, x-y Taylor-Green boxes as nx x ny x 1
+runs) or on light-cone samples.  Norms: max |du| / max |u_ref|, ||du||_2 /
+||u_ref||_2, max |drho|, ||drho||_2 / ||rho_ref||_2, and for waves on a
+background U also max |du| / max |u_ref - U|.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -79,21 +91,26 @@ KERNEL_SYMBOLS = {"scalar": "k_step", "row_wave": "k_step_vec", "in_place": "k_s
                   "twist": "k_step_tw"}
 
 
+MAX_GRAPH_CHUNK = 4096
+
+
 def measure_box(lattice, dims, tau, dtype, rho, u, steps, warmup, tune=True, **kw):
     """Create, initialise, autotune the launch (outside the timed region, state
-    restored), then time `steps` steps.  The FP64 totals (lbm_totals) before
-    and after give the mass and momentum drift over all the steps taken."""
+    restored), then time `steps` steps, issued as graphs of min(steps, 4096)
+    steps.  The FP64 totals (lbm_totals) before and after give the mass and
+    momentum drift over all the steps taken."""
     import numpy as np
 
     from paper_2002_02503_amd import lbm
 
-    with lbm.Simulation(lattice, dims, tau, dtype=dtype, **kw) as sim:
+    chunk = min(steps, MAX_GRAPH_CHUNK)
+    with lbm.Simulation(lattice, dims, tau, dtype=dtype, graph_chunk=chunk, **kw) as sim:
         t0 = time.perf_counter()
         sim.init(rho, u)  # host fields in, synchronises
         init_ms = (time.perf_counter() - t0) * 1e3
         tot0 = sim.totals()
         if tune:
-            sim.tune(steps=10)
+            sim.tune(steps=20)
         ms = timed_steps(sim, steps, warmup)
         tot1 = sim.totals()
         t0 = time.perf_counter()
@@ -112,6 +129,8 @@ def measure_box(lattice, dims, tau, dtype, rho, u, steps, warmup, tune=True, **k
             "bytes_per_site_update": bytes_site, "nsites": nsites, "achieved_GBs": gbs,
             "roofline_frac": gbs / PEAK_HBM_GBS, "kernel": KERNEL_NAMES[info["kernel"]],
             "block": info["block"], "grid": info["grid"], "conservation": conservation,
+            "launches": {"graph_chunk": int(info["graph_chunk"]), "graph_launches": steps // int(info["graph_chunk"]),
+                         "direct_launches": steps % int(info["graph_chunk"]), "warmup_direct_launches": warmup},
             "host_io_ms": {"init": init_ms, "moments": moments_ms}}
 
 
@@ -153,23 +172,32 @@ def cpu_model() -> str:
     return "unknown"
 
 
+def err_norms(r, uu, r_ref, u_ref, U=None) -> dict:
+    """Error norms of (rho, u) against the oracle's fields (see the module
+    docstring); U: the background velocity of a wave."""
+    import numpy as np
+
+    du, dr = uu - u_ref, r - r_ref
+    e = {"u_max_rel": float(np.abs(du).max() / np.abs(u_ref).max()),
+         "u_l2_rel": float(np.sqrt(np.sum(du * du) / np.sum(u_ref * u_ref))),
+         "rho_max": float(np.abs(dr).max()),
+         "rho_l2_rel": float(np.sqrt(np.sum(dr * dr) / np.sum(r_ref * r_ref)))}
+    if U is not None:
+        Ub = np.asarray(U, dtype=np.float64)[: u_ref.shape[0]].reshape((-1,) + (1,) * (u_ref.ndim - 1))
+        e["u_max_rel_to_wave"] = float(np.abs(du).max() / np.abs(u_ref - Ub).max())
+    return e
+
+
 def cpu_baseline_leg(rho, u, tau, budget_s: float, dtypes):
     """The FP64 oracle as it stands, on the full 256^3 box, for as many steps as
     fit in about `budget_s` seconds of host time -- timed as the CPU baseline.
     Its fields after those steps, and a 500-step oracle run of the same recipe
     at 32^3, are the references for the error statement of every storage type
-    (max and L2 error of u and rho)."""
-    import numpy as np
-
+    (max and L2 error of u and rho).  The 500-step error at 256^3 itself takes
+    minutes of host time and is measured by the GPU test suite
+    (test_turbulence_256_full_horizon_error)."""
     import oracle
     from paper_2002_02503_amd import inputs, lbm
-
-    def errs(r, uu, r_ref, u_ref):
-        du, dr = uu - u_ref, r - r_ref
-        return {"u_max_rel": float(np.abs(du).max() / np.abs(u_ref).max()),
-                "u_l2_rel": float(np.sqrt(np.sum(du * du) / np.sum(u_ref * u_ref))),
-                "rho_max": float(np.abs(dr).max()),
-                "rho_l2_rel": float(np.sqrt(np.sum(dr * dr) / np.sum(r_ref * r_ref)))}
 
     t0 = time.perf_counter()
     sim = oracle.Sim("D3Q19", (256, 256, 256), tau)
@@ -190,25 +218,184 @@ def cpu_baseline_leg(rho, u, tau, budget_s: float, dtypes):
             "cpu_model": cpu_model()}
     r_ref, u_ref = sim.moments()
     del sim
-    errors = {}
+    errors = {"bounds": dict(lbm.STATED_BOUNDS),
+              "bound_norm": "max |u - u_oracle| / max |u_oracle| and max |rho - rho_oracle|",
+              f"full_256cubed_{steps}_steps": {}, "recipe_32cubed_500_steps": {}}
     for dt in dtypes:
         log(f"error statement {dt}: 256^3 after {steps} steps")
         with lbm.Simulation("D3Q19", (256, 256, 256), tau, dtype=dt) as g:
             g.init(rho, u).step(steps)
             r, uu = g.moments()
-        errors[dt] = {f"full_256cubed_{steps}_steps": errs(r, uu, r_ref, u_ref)}
+        errors[f"full_256cubed_{steps}_steps"][dt] = err_norms(r, uu, r_ref, u_ref)
         del r, uu
     del r_ref, u_ref
     log("error statement: 32^3 same recipe, 500 steps")
     srho, su = inputs.turbulence(32)
-    ref = oracle.Sim("D3Q19", (32, 32, 32), tau).init(srho, su).step(500)
+    ref = oracle.Sim("D3Q19", (32, 32, 32), tau, mode="closed").init(srho, su).step(500)
     r_ref, u_ref = ref.moments()
     for dt in dtypes:
         with lbm.Simulation("D3Q19", (32, 32, 32), tau, dtype=dt) as g:
             g.init(srho, su).step(500)
             r, uu = g.moments()
-        errors[dt]["recipe_32cubed_500_steps"] = errs(r, uu, r_ref, u_ref)
+        errors["recipe_32cubed_500_steps"][dt] = err_norms(r, uu, r_ref, u_ref)
     return base, errors
+
+
+def _row_amplitude(u_row, U_y: float) -> complex:
+    """Complex amplitude of the first Fourier mode of u_y - U_y along one x-row."""
+    import numpy as np
+
+    n = u_row.shape[0]
+    return complex(np.mean((u_row - U_y) * np.exp(-2j * np.pi * np.arange(n) / n)))
+
+
+def _decay_rate(ts, amps) -> float:
+    """Least-squares slope of -log|amplitude| over the last 80% of the run."""
+    import numpy as np
+
+    ts = np.asarray(ts, dtype=np.float64)
+    a = np.log(np.abs(np.asarray(amps)))
+    sel = ts >= 0.2 * ts.max()
+    return -float(np.polyfit(ts[sel], a[sel], 1)[0])
+
+
+def shear_run_gpu(lattice, n, tau, U, steps, dtype="fp32", every=100, **kw):
+    """GPU shear wave (amplitude 0.01 along y on background U) on an n^3 box:
+    decay rate of its fundamental mode and the final fields (one x-row each,
+    the field being x-only bit for bit)."""
+    import torch
+
+    from paper_2002_02503_amd import inputs, lbm
+
+    rho, u = inputs.shear_wave((n, n, n), 0.01, U)
+    ts, amps = [0], [_row_amplitude(u[1, 0, 0], U[1])]
+    with lbm.Simulation(lattice, (n, n, n), tau, dtype=dtype, graph_chunk=every, **kw) as sim:
+        sim.init(rho, u)
+        for t in range(every, steps + 1, every):
+            sim.step(every)
+            r, uu = sim.moments(device=True)
+            ts.append(t)
+            amps.append(_row_amplitude(uu[1, 0, 0].cpu().numpy(), U[1]))
+        x_only = bool(torch.equal(uu, uu[:, :1, :1, :].expand_as(uu)))
+        row = (r[0, 0].cpu().numpy()[None, None, :], uu[:, 0, 0].cpu().numpy()[:, None, None, :])
+    return _decay_rate(ts, amps), row, x_only
+
+
+def shear_run_oracle(lattice, n, tau, U, steps, every=100, **kw):
+    """The oracle's run of the same x-only wave on an n x 1 x 1 box."""
+    import oracle
+    from paper_2002_02503_amd import inputs
+
+    rho, u = inputs.shear_wave((n, 1, 1), 0.01, U)
+    sim = oracle.Sim(lattice, (n, 1, 1), tau, mode="closed", **kw).init(rho, u)
+    ts, amps = [0], [_row_amplitude(u[1, 0, 0], U[1])]
+    for t in range(every, steps + 1, every):
+        sim.step(every)
+        _, uu = sim.moments()
+        ts.append(t)
+        amps.append(_row_amplitude(uu[1, 0, 0], U[1]))
+    return _decay_rate(ts, amps), sim.moments()
+
+
+def galilean_leg():
+    """The Galilean test of configs with a background flow, on the GPU beside
+    the oracle: the relative change of a shear wave's decay rate when the
+    uniform flow U is added, |gamma_U / gamma_0 - 1|.  D3Q19 128^3, tau = 0.55,
+    U = (0.1, 0.05, 0), 2000 steps, the paper's operator (K = 3) against the
+    zero-velocity filter (K = 2), in FP32 and FP64; D3Q39 (K = 4) against
+    D3Q19 at 192^3, tau = 0.6, U = (0.2, 0, 0), 1000 steps, in FP32 and FP64.
+    In FP32 the rate fit bottoms out near 1e-4 (the wave decays by only a few
+    per cent over the run); the FP64 runs resolve the operator's own ~1e-5.
+    Also the shear waves' own errors against the oracle at the last step."""
+    out = {}
+    cases = [("d3q19_128_U0.1_0.05", "D3Q19", 128, 0.55, (0.1, 0.05, 0.0), 2000, "fp32", {}),
+             ("d3q19_128_U0.1_0.05_fp64", "D3Q19", 128, 0.55, (0.1, 0.05, 0.0), 2000, "fp64", {}),
+             ("d3q19_128_U0.1_0.05_k2", "D3Q19", 128, 0.55, (0.1, 0.05, 0.0), 2000, "fp32", {"K": 2}),
+             ("d3q39_192_U0.2", "D3Q39", 192, 0.6, (0.2, 0.0, 0.0), 1000, "fp32", {}),
+             ("d3q19_192_U0.2", "D3Q19", 192, 0.6, (0.2, 0.0, 0.0), 1000, "fp32", {}),
+             ("d3q39_192_U0.2_fp64", "D3Q39", 192, 0.6, (0.2, 0.0, 0.0), 1000, "fp64", {}),
+             ("d3q19_192_U0.2_fp64", "D3Q19", 192, 0.6, (0.2, 0.0, 0.0), 1000, "fp64", {})]
+    for name, lat, n, tau, U, steps, dt, kw in cases:
+        log(f"Galilean test {name}: {lat} {n}^3 {dt}, {steps} steps, U and U = 0")
+        gU, (rU, uU), x_only = shear_run_gpu(lat, n, tau, U, steps, dtype=dt, **kw)
+        g0, _, _ = shear_run_gpu(lat, n, tau, (0.0, 0.0, 0.0), steps, dtype=dt, **kw)
+        oU, (r_ref, u_ref) = shear_run_oracle(lat, n, tau, U, steps, **kw)
+        o0, _ = shear_run_oracle(lat, n, tau, (0.0, 0.0, 0.0), steps, **kw)
+        out[name] = {"lattice": lat, "n": n, "tau": tau, "U": list(U), "steps": steps, "dtype": dt,
+                     "hermite_order": kw.get("K", 4 if lat == "D3Q39" else 3),
+                     "galilean_rel_rate_change_gpu": gU / g0 - 1, "galilean_rel_rate_change_oracle": oU / o0 - 1,
+                     "decay_rate_gpu": gU, "decay_rate_oracle": oU, "x_only_bitwise": x_only,
+                     "error_at_last_step": err_norms(rU, uU, r_ref, u_ref, U=U)}
+    return out
+
+
+def variant_error_leg():
+    """Error statements of the benchmark's variants against the oracle:
+    the 256-box batch (every 16th box against its nx x ny x 1 reduction after
+    1000 steps), D3Q39 192^3 at K = 5 (300 steps, 192 x 1 x 1 reduction), and
+    the collision kinds and D3Q15 on the 256^3 turbulence box (24 light-cone
+    samples after 3 steps).  The D3Q39 K = 4 and FP64 statements come from the
+    Galilean leg and the CPU baseline leg."""
+    import numpy as np
+
+    import oracle
+    from paper_2002_02503_amd import inputs, lbm
+
+    out = {}
+    log("error statement: 256-box batch, 1000 steps, 16 boxes against the oracle")
+    boxes = inputs.batch_boxes()
+    dims, taus, rho, u = batch_fields()
+    with lbm.Simulation("D3Q19", dims, taus, dtype="fp32", graph_chunk=1000) as sim:
+        sim.init(rho, u).step(1000)
+        r, uu = sim.moments()
+        rb, ub = sim.split_boxes(r), sim.split_boxes(uu)
+    del rho, u
+    worst = {}
+    for k in range(0, len(boxes), 16):
+        nx, ny, _ = boxes[k]["dims"]
+        r1, u1 = inputs.taylor_green_box((nx, ny, 1), boxes[k]["U"], 1.0 / 3.0)
+        ref = oracle.Sim("D3Q19", (nx, ny, 1), boxes[k]["tau"], mode="closed").init(r1, u1).step(1000)
+        r_ref, u_ref = ref.moments()
+        e = err_norms(rb[k][:1], ub[k][:, :1], r_ref, u_ref)
+        # most vortices have decayed to round-off by t = 1000: relate the
+        # error to the initial vortex amplitude instead of the final one
+        Ub = np.asarray(boxes[k]["U"]).reshape(3, 1, 1, 1)
+        e["u_max_rel_to_initial_wave"] = float(np.abs(ub[k][:, :1] - u_ref).max() / np.abs(u1 - Ub).max())
+        for key, v in e.items():
+            worst[key] = max(worst.get(key, 0.0), v)
+    out["batched_fp32"] = dict(worst, horizon_steps=1000, note="worst of boxes 0, 16, ..., 240 (per-box norms) "
+                                                                "against their nx x ny x 1 oracle runs")
+    log("error statement: D3Q39 192^3 K = 5, 300 steps")
+    U = (0.2, 0.0, 0.0)
+    srho, su = inputs.shear_wave((192, 192, 192), 0.01, U)
+    with lbm.Simulation("D3Q39", (192, 192, 192), 0.6, dtype="fp32", K=5) as sim:
+        sim.init(srho, su).step(300)
+        r, uu = sim.moments()
+    del srho, su
+    r1, u1 = inputs.shear_wave((192, 1, 1), 0.01, U)
+    # the closed forms are printed up to K = 4: the literal Hermite-tensor mode
+    r_ref, u_ref = oracle.Sim("D3Q39", (192, 1, 1), 0.6, K=5, mode="literal").init(r1, u1).step(300).moments()
+    out["d3q39_k5_fp32_192"] = dict(err_norms(r[:1, :1], uu[:, :1, :1], r_ref, u_ref, U=U), horizon_steps=300,
+                                    x_only_bitwise=bool(np.array_equal(uu, np.broadcast_to(uu[:, :1, :1], uu.shape))))
+    del r, uu
+    log("error statement: collision kinds and D3Q15 on the 256^3 turbulence box, 24 light-cone samples, 3 steps")
+    rho, u = inputs.turbulence(256)
+    rng = np.random.default_rng(2)
+    pts = [(0, 0, 0), (255, 255, 255)] + [tuple(int(v) for v in rng.integers(0, 256, 3)) for _ in range(22)]
+    idx = tuple(np.array(pts).T)
+    for name, lat, lib_kw, ora_kw in [("d3q19_bgk_fp32_256", "D3Q19", {"collision": "bgk"}, {"kind": "bgk"}),
+                                      ("d3q19_theta0.5_fp32_256", "D3Q19", {"theta": 0.5},
+                                       {"theta": 0.5, "mode": "literal"}),
+                                      ("d3q19_k2_fp32_256", "D3Q19", {"K": 2}, {"K": 2}),
+                                      ("d3q15_fp32_256", "D3Q15", {}, {})]:
+        r_ref, u_ref = oracle.lightcone_samples(lat, rho, u, 0.51, 3, pts, **ora_kw)
+        with lbm.Simulation(lat, (256, 256, 256), 0.51, dtype="fp32", **lib_kw) as sim:
+            sim.init(rho, u).step(3)
+            r, uu = sim.moments()
+        out[name] = dict(err_norms(r[idx], uu[(slice(None),) + idx], r_ref, u_ref), horizon_steps=3,
+                         note="24 sampled sites, light-cone oracle values")
+        del r, uu
+    return out
 
 
 def main():
@@ -219,6 +406,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true", help="headline FP32 measurement only")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle leg (CPU baseline timing and error statements)")
+    ap.add_argument("--no-errors", action="store_true",
+                    help="skip the variants' error statements and the Galilean test (oracle on reductions)")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle stepping")
     ap.add_argument("--kernel", choices=["tune", "scalar", "row_wave", "in_place", "two_row", "twist"],
                     default="tune",
@@ -317,11 +506,25 @@ def main():
             v["traffic_over_algorithmic"] = tb / (v["bytes_per_site_update"] * v["nsites"]) if tb else None
             v["traffic_source"] = src
 
+    galilean = None
+    if not args.no_errors and not args.no_variants:
+        galilean = galilean_leg()
+        verr = variant_error_leg()
+        for name, e in verr.items():
+            variants[name]["error"] = e
+        variants["d3q39_fp32_192"]["error"] = dict(galilean["d3q39_192_U0.2"]["error_at_last_step"],
+                                                   horizon_steps=1000)
+
     cpu, errors = None, {}
     if not args.no_cpu_baseline:
         log("CPU baseline leg: FP64 oracle on the host cores, and the error statements")
-        dts = ["fp32", "fp16", "bf16"] if not args.no_variants else ["fp32"]
+        dts = ["fp32", "fp16", "bf16", "fp64"] if not args.no_variants else ["fp32"]
         cpu, errors = cpu_baseline_leg(rho, u, tau, args.cpu_budget, dts)
+        full = [k for k in errors if k.startswith("full_256cubed_")]
+        for dt in ["fp16", "bf16", "fp64"]:
+            if full and dt in variants and dt in errors[full[0]]:
+                variants[dt]["error"] = dict(errors[full[0]][dt], horizon_steps=int(full[0].split("_")[2]),
+                                             bound=errors["bounds"][dt])
 
     line = {
         "metric": METRIC,
@@ -345,8 +548,10 @@ def main():
         "cpu_baseline": cpu,
         "copy_probe": {"bytes_moved": 2 * copy_bytes, "GB_s": copy_gbs, "frac_of_peak": copy_gbs / PEAK_HBM_GBS},
         "frac_of_copy": head["achieved_GBs"] / copy_gbs,
+        "launches": head["launches"],
         "variants": variants,
         "errors": errors,
+        "galilean": galilean,
     }
     print(json.dumps(line), flush=True)
 

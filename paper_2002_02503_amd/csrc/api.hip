@@ -1024,12 +1024,20 @@ lbm_status lbm_tune(lbm_t h, int32_t steps, const char* cache_path)
 
         // tuning steps the state: keep a copy and restore it afterwards; the
         // candidates switch kernels, so start from the natural layout in buf[0]
+        const LaunchChoice old = {h->kernel, h->block, h->grid};
         if (lbm_status st = canonicalize(h)) return st;
         const int cur0 = h->cur;
         const int64_t t0 = h->t;
-        const LaunchChoice old = {h->kernel, h->block, h->grid};
         void* saved = nullptr;
-        HIP_TRY(hipMalloc(&saved, h->state_bytes), "hipMalloc(tuning copy)");
+        if (hipError_t me = hipMalloc(&saved, h->state_bytes)) {
+            lbm_status fst = fail_hip(me, "hipMalloc(tuning copy)");
+            (void)apply_choice(h, old);
+            return fst;
+        }
+        // candidates are timed on direct launches: a graph built inside the
+        // timed window would charge its capture to one candidate
+        const int chunk0 = h->graph_chunk;
+        h->graph_chunk = 1;
         hipEvent_t e0 = nullptr, e1 = nullptr;
         hipError_t e = hipMemcpyAsync(saved, h->buf[cur0], h->state_bytes, hipMemcpyDeviceToDevice, h->stream);
         if (e == hipSuccess) e = hipEventCreate(&e0);
@@ -1069,6 +1077,7 @@ lbm_status lbm_tune(lbm_t h, int32_t steps, const char* cache_path)
         h->kernel = LBM_KERNEL_SCALAR;
         h->cur = cur0;
         h->t = t0;
+        h->graph_chunk = chunk0;
         if (st != LBM_OK) {
             (void)apply_choice(h, old);
             return st;

@@ -33,6 +33,15 @@ EXPORTS = ["lbm_create", "lbm_create_batch", "lbm_set_hermite_order", "lbm_set_c
            "lbm_copy_probe"]
 
 
+# Stated error bounds of each storage type: the largest velocity error
+# max |u - u_oracle| / max |u_oracle| (and density error max |rho -
+# rho_oracle|) against the FP64 oracle on the same seeded inputs.  FP64 and
+# FP32 are the method's tolerances; FP16 and BF16 store S (f_i - w_i) with 11
+# and 8 significant bits and are bounded by what the 500-step 256^3
+# turbulence run and the 2000-step shear waves measure, with margin.
+STATED_BOUNDS = {"fp64": 1e-12, "fp32": 1e-5, "fp16": 5e-3, "bf16": 5e-2}
+
+
 class LBMError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"{STATUS.get(status, status)}: {message}")

@@ -1,12 +1,6 @@
 """Helpers shared by the GPU tests: running the library and the oracle on the
-same seeded inputs, and computing sampled oracle values at full size.
-
-Light-cone sampling: the populations at site x after s steps depend only on
-the initial fields within R*s sites of x (R = largest velocity component).
-Running the oracle on a periodic box of side 2*R*s + 1 centred on x (cut out
-of the full initial field) therefore gives the exact value at its centre: the
-wrap-around of the small box contaminates only layers closer than R*s to its
-faces."""
+same seeded inputs, and sampled oracle values at full size through the light
+cone (oracle.lightcone_samples)."""
 from __future__ import annotations
 
 import numpy as np
@@ -14,10 +8,9 @@ import numpy as np
 import oracle
 from paper_2002_02503_amd import lbm
 
-# Stated error bounds of the reduced-precision storage modes (max |du| over
-# max |u| against the FP64 oracle).  FP64 and FP32 use the tolerances of the
-# method's specification: 1e-12 and 1e-5 relative.
-BOUND = {"fp64": 1e-12, "fp32": 1e-5, "fp16": 5e-3, "bf16": 5e-2}
+# The library's stated error bounds per storage type (max |du| over max |u|
+# against the FP64 oracle): 1e-12 (FP64), 1e-5 (FP32), 5e-3 (FP16), 5e-2 (BF16).
+BOUND = dict(lbm.STATED_BOUNDS)
 
 
 def rel_u(u, u_ref) -> float:
@@ -41,29 +34,8 @@ def run_oracle(lattice, dims, tau, rho, u, steps, K=None, mode="literal", **kw):
 
 
 def lightcone_samples(lattice, rho0, u0, tau, steps, points, K=None, mode="closed", **kw):
-    """Oracle (rho, u) at `points` (list of (z, y, x)) after `steps` steps of a
-    run started from (rho0, u0) on the full periodic box.  Further keywords
-    (kind, theta) go to the oracle's Sim."""
-    L = oracle.lattice(lattice)
-    D = L["D"]
-    R = int(np.abs(L["c"]).max())
-    r = R * steps
-    nz, ny, nx = rho0.shape
-    side = 2 * r + 1
-    rho_out, u_out = [], []
-    for z, y, x in points:
-        ix = (x + np.arange(-r, r + 1)) % nx
-        iy = (y + np.arange(-r, r + 1)) % ny
-        iz = (z + np.arange(-r, r + 1)) % nz if D == 3 else np.array([0])
-        sub_r = rho0[np.ix_(iz, iy, ix)]
-        sub_u = u0[(slice(None),) + np.ix_(iz, iy, ix)]
-        dims = (side, side, side if D == 3 else 1)
-        sim = oracle.Sim(lattice, dims, tau, K=K, mode=mode, **kw).init(sub_r, sub_u).step(steps)
-        rr, uu = sim.moments()
-        cz = r if D == 3 else 0
-        rho_out.append(rr[cz, r, r])
-        u_out.append(uu[:, cz, r, r])
-    return np.array(rho_out), np.array(u_out).T
+    """Oracle (rho, u) at `points` after `steps` steps (oracle.lightcone_samples)."""
+    return oracle.lightcone_samples(lattice, rho0, u0, tau, steps, points, K=K, mode=mode, **kw)
 
 
 def sample_points(shape, n, seed):

@@ -424,3 +424,22 @@ def test_literal_and_closed_modes_agree_over_steps(oracle_mod):
             s.step(20)
         assert np.abs(sims[0].populations() - sims[1].populations()).max() < 1e-15
     del inputs
+
+
+@pytest.mark.parametrize("name,n,steps", [("D3Q19", 24, 3), ("D3Q39", 22, 2), ("D2Q9", 30, 4)])
+def test_lightcone_samples_equal_the_full_run(oracle_mod, name, n, steps):
+    """Sampled values through the light cone (the full-size GPU checks use
+    them) are exactly the full periodic run's values at those sites."""
+    O = oracle_mod
+    D = O.lattice(name)["D"]
+    rng = np.random.default_rng(7)
+    shape = (n, n, n) if D == 3 else (1, n, n)
+    rho = 1.0 + rng.uniform(-0.01, 0.01, size=shape)
+    u = rng.uniform(-0.05, 0.05, size=(D,) + shape)
+    dims = (n, n, n if D == 3 else 1)
+    r_full, u_full = O.Sim(name, dims, 0.6, mode="closed").init(rho, u).step(steps).moments()
+    pts = [(0, 0, 0), (shape[0] - 1, 5, n - 1), (0 if D == 2 else 7, n - 2, 3)]
+    r_s, u_s = O.lightcone_samples(name, rho, u, 0.6, steps, pts)
+    for k, p in enumerate(pts):
+        assert r_s[k] == r_full[p]
+        assert np.array_equal(u_s[:, k], u_full[(slice(None),) + p])
