@@ -49,9 +49,9 @@ def traffic_file(kernel: str, workload: str = "turbulence256", dtype: str = "fp3
 # what decides the step kernel's machine code: its sources and the compiler flags
 def _kernel_sources() -> list:
     """Every source that goes into the device code (all of csrc/ except the
-    host-only C-ABI file), and the build flags."""
+    host-only C-ABI and host-helper files), and the build flags."""
     csrc = os.path.join(ROOT, "paper_2002_02503_amd", "csrc")
-    names = sorted(n for n in os.listdir(csrc) if n.endswith((".hip", ".hpp")) and n != "api.hip")
+    names = sorted(n for n in os.listdir(csrc) if n.endswith((".hip", ".hpp")) and n not in ("api.hip", "host.hpp"))
     return [f"csrc/{n}" for n in names] + ["build.py"]
 
 

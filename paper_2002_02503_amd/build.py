@@ -22,7 +22,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "liblbm.so")
-SOURCES = ["kernels.hip", "api.hip"]
+SOURCES = ["kernels.hip", "api.hip", "host.cpp"]
 STORAGE = ["double", "float", "_Float16", "bf16_t"]
 # Step-kernel instances, one translation unit per group (lattice, storage
 # types): the large D3Q39 instances get a unit per storage type so that the
@@ -77,7 +77,7 @@ def build(out: str = LIB) -> str:
     gendir = os.path.join(objdir, "gen")
     os.makedirs(gendir, exist_ok=True)
     srcs = [os.path.join(CSRC, s) for s in SOURCES] + _instance_units(gendir)
-    objs = [os.path.join(objdir, os.path.basename(s).replace(".hip", ".o")) for s in srcs]
+    objs = [os.path.join(objdir, os.path.splitext(os.path.basename(s))[0] + ".o") for s in srcs]
     workers = min(len(srcs), max(1, os.cpu_count() or 1), 16)
     with cf.ThreadPoolExecutor(max_workers=workers) as ex:
         list(ex.map(_compile, srcs, objs))

@@ -54,21 +54,8 @@ lbm_status fail_hip(hipError_t e, const char* what)
     } while (0)
 
 constexpr int kChunkSites = 4096;   // sites per reduction chunk
-constexpr int kBlockSites = 64;     // sites per block of a batched box's layout (one wave)
-constexpr int64_t kMaxSites = int64_t(1) << 36;  // total sites: keeps chunk and tile counts in int
 constexpr int kDefaultGraphChunk = 32;
 constexpr int kTuneRounds = 3;
-constexpr uint64_t kCkptMagic = 0x314b4350434d424cULL;  // "LBMCPCK1"
-
-struct CkptHeader {
-    uint64_t magic;
-    int32_t lattice, dtype, K, nbox;
-    int64_t nsites, t;
-    uint64_t geometry_hash;
-    uint64_t payload_bytes;
-    uint64_t reserved;  // keeps the header 64 bytes, so the payload is 64-byte aligned
-};
-static_assert(sizeof(CkptHeader) == 64, "checkpoint header layout");
 
 // Scratch of the allocation-free residual (lbm_residual_noalloc): the
 // per-chunk partial sums of the residual kernels, 4 doubles per reduction
@@ -169,17 +156,7 @@ int effective_block(const lbm_ctx* h)
     return int(b);
 }
 
-uint64_t geometry_hash(const lbm_ctx* h)
-{
-    uint64_t x = 1469598103934665603ULL;  // FNV-1a over the dims
-    for (int64_t d : h->dims) {
-        for (int k = 0; k < 8; ++k) {
-            x ^= uint64_t((d >> (8 * k)) & 0xff);
-            x *= 1099511628211ULL;
-        }
-    }
-    return x;
-}
+uint64_t geometry_hash(const lbm_ctx* h) { return lbm::geometry_hash(h->dims); }
 
 lbm_status check_handle(lbm_t h)
 {
@@ -212,20 +189,6 @@ void free_all(lbm_ctx* h)
     (void)hipFree(h->d_out);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     h->cap_stream = nullptr;
-}
-
-lbm_status validate_box(int lattice, const int64_t* d, double tau, const LatticeInfo& L, int index)
-{
-    for (int a = 0; a < 3; ++a) {
-        if (d[a] < 1 || d[a] > INT32_MAX)
-            return fail(LBM_EINVAL, "box %d: dims[%d] = %lld outside [1, 2^31)", index, a, (long long)d[a]);
-    }
-    // the step kernels index x-rows r = z ny + y in 32 bits
-    if (d[1] * d[2] > INT32_MAX) return fail(LBM_EINVAL, "box %d: ny * nz must be below 2^31", index);
-    if (L.D == 2 && d[2] != 1) return fail(LBM_EINVAL, "box %d: a 2-D lattice needs nz == 1", index);
-    if (!std::isfinite(tau) || !(tau > 0.5)) return fail(LBM_EINVAL, "box %d: tau must be finite and > 1/2", index);
-    (void)lattice;
-    return LBM_OK;
 }
 
 lbm_status device_check(int* dev)
@@ -302,28 +265,8 @@ lbm_status create_common(lbm_t* out, int32_t lattice, int32_t nbox, const int64_
     if (nbox < 1) return fail(LBM_EINVAL, "nbox must be >= 1");
     if (!dims || !tau) return fail(LBM_EINVAL, "dims or tau is NULL");
     // every argument is checked here, on the host, before any device call
-    int64_t total = 0;
-    for (int b = 0; b < nbox; ++b) {
-        lbm_status st = validate_box(lattice, dims + 3 * b, tau[b], L, b);
-        if (st != LBM_OK) return st;
-        const int64_t nx = dims[3 * b], ny = dims[3 * b + 1], nz = dims[3 * b + 2];
-        total += nx * ny * nz;
-        if (total > kMaxSites) return fail(LBM_EINVAL, "total site count must be at most 2^36");
-        // lane offsets inside one population row are formed in 32 bits
-        if (nx * int64_t(storage_bytes(dtype)) > INT32_MAX)
-            return fail(LBM_EINVAL, "box %d: a population row (nx * storage bytes) must be below 2 GiB", b);
-        // y and z are grid coordinates of the single-box kernels
-        if (ny > 65535 || nz > 65535) return fail(LBM_EINVAL, "box %d: ny and nz must be at most 65535", b);
-        if (nbox > 1) {
-            // a batch box is addressed with 32-bit element offsets
-            const uint64_t padded = (uint64_t(nx * ny * nz) + kBlockSites - 1) / kBlockSites * kBlockSites;
-            if (padded * uint64_t(L.Q) * storage_bytes(dtype) >= (uint64_t(1) << 31))
-                return fail(LBM_EINVAL, "box %d of a batch must hold less than 2 GiB of populations", b);
-            // the batched step splits a lane's site with a float reciprocal,
-            // exact while x0 + 64 stays below 2^22
-            if (nx > (int64_t(1) << 21)) return fail(LBM_EINVAL, "box %d of a batch: nx must be at most 2^21", b);
-        }
-    }
+    std::string why;
+    if (!check_boxes(L, dtype, nbox, dims, tau, &why)) return fail(LBM_EINVAL, "%s", why.c_str());
     int dev = 0;
     lbm_status st = device_check(&dev);
     if (st != LBM_OK) return st;
@@ -571,37 +514,10 @@ lbm_status enter_kernel_layout(lbm_ctx* h)
 }
 
 // Host copy of a single box's state between an in-place layout and the
-// natural one (to_natural: src in `layout`, dst natural; else the reverse).
-// Population i of site x is at x + o_i, tile row r_i: o_i = c_i, r_i =
-// m(opp(i)) when swapped; o_i = b_i (positive part of c_i), r_i = m(i) or
-// m(opp(i)) when twisted at an even or odd time.
+// natural one (host.hpp, relayout_host).
 void relayout_host(const lbm_ctx* h, int layout, bool to_natural, const char* src, char* dst)
 {
-    const LatticeInfo& L = h->lat;
-    const int64_t nx = h->dims[0], ny = h->dims[1], nz = h->dims[2];
-    const size_t e = h->elem;
-    const int64_t tile = int64_t(L.Q) * nx;
-    auto wrap = [](int64_t v, int64_t n) { return ((v % n) + n) % n; };
-    for (int j = 0; j < L.Q; ++j) {
-        const int jo = (j == 0) ? 0 : ((j & 1) ? j + 1 : j - 1);
-        int64_t o[3];
-        for (int a = 0; a < 3; ++a) {
-            const int c = L.c[j * 3 + a];
-            o[a] = (layout == kSwapped) ? c : (c > 0 ? c : 0);
-        }
-        const int64_t r = (layout == kTwistEven) ? L.mrow[j] : L.mrow[jo];
-        for (int64_t z = 0; z < nz; ++z)
-            for (int64_t y = 0; y < ny; ++y) {
-                const int64_t zs = wrap(z + o[2], nz), ys = wrap(y + o[1], ny);
-                const int64_t lay_row = (zs * ny + ys) * tile + r * nx;
-                const int64_t nat_row = (z * ny + y) * tile + int64_t(L.mrow[j]) * nx;
-                for (int64_t x = 0; x < nx; ++x) {
-                    const int64_t xs = wrap(x + o[0], nx);
-                    if (to_natural) std::memcpy(dst + (nat_row + x) * e, src + (lay_row + xs) * e, e);
-                    else std::memcpy(dst + (lay_row + xs) * e, src + (nat_row + x) * e, e);
-                }
-            }
-    }
+    lbm::relayout_host(h->lat, h->dims[0], h->dims[1], h->dims[2], h->elem, layout, to_natural, src, dst);
 }
 
 lbm_status build_graph(lbm_ctx* h, int parity)
@@ -923,9 +839,6 @@ lbm_status lbm_step(lbm_t h, int64_t n)
 
 namespace {
 
-struct LaunchChoice {
-    int kernel, block, grid;
-};
 
 std::string tune_key(const lbm_ctx* h)
 {
@@ -934,32 +847,6 @@ std::string tune_key(const lbm_ctx* h)
              h->lattice, h->dtype, h->K, step_kind(h), h->nbox, (long long)h->nsites,
              (unsigned long long)geometry_hash(h));
     return buf;
-}
-
-bool cache_lookup(const char* path, const std::string& key, LaunchChoice* out)
-{
-    if (!path || !*path) return false;
-    std::ifstream in(path);
-    std::string line;
-    bool found = false;
-    while (std::getline(in, line)) {
-        const size_t bar = line.find(" | ");
-        if (bar == std::string::npos || line.compare(0, bar, key) != 0 || bar != key.size()) continue;
-        std::istringstream rest(line.substr(bar + 3));
-        LaunchChoice c;
-        if (rest >> c.kernel >> c.block >> c.grid) {
-            *out = c;  // the last entry for a key wins
-            found = true;
-        }
-    }
-    return found;
-}
-
-void cache_store(const char* path, const std::string& key, const LaunchChoice& c)
-{
-    if (!path || !*path) return;
-    std::ofstream out(path, std::ios::app);
-    out << key << " | " << c.kernel << " " << c.block << " " << c.grid << "\n";
 }
 
 // Switch the launch; the state is first brought into the natural layout in
@@ -987,7 +874,7 @@ lbm_status lbm_tune(lbm_t h, int32_t steps, const char* cache_path)
         if (!cache_path) cache_path = std::getenv("LBM_TUNE_CACHE");
         const std::string key = tune_key(h);
         LaunchChoice best;
-        if (cache_lookup(cache_path, key, &best)) {
+        if (tune_cache_lookup(cache_path, key, &best)) {
             // the cache is a text file: take only values this library can launch
             if (best.kernel < LBM_KERNEL_AUTO || best.kernel > LBM_KERNEL_TWIST) best.kernel = LBM_KERNEL_SCALAR;
             if (!(best.block == 0 || (best.block >= 64 && best.block <= 256 && best.block % 64 == 0))) best.block = 0;
@@ -1084,7 +971,7 @@ lbm_status lbm_tune(lbm_t h, int32_t steps, const char* cache_path)
         }
         if (re != hipSuccess) return fail_hip(re, "restoring the state after tuning");
         if (lbm_status ast = apply_choice(h, best)) return ast;
-        cache_store(cache_path, key, best);
+        tune_cache_store(cache_path, key, best);
         return LBM_OK;
     } catch (const std::bad_alloc&) {
         return fail(LBM_ENOMEM, "lbm_tune: host memory allocation failed");
@@ -1295,13 +1182,19 @@ lbm_status lbm_set_state(lbm_t h, const void* buf, size_t bytes)
         if (lbm_status st = check_handle(h)) return st;
         size_t need = 0;
         lbm_checkpoint_bytes(h, &need);
-        if (!buf || bytes < need) return fail(LBM_EINVAL, "checkpoint buffer needs %zu bytes", need);
+        CkptHeader expect;
+        std::memset(&expect, 0, sizeof(expect));
+        expect.lattice = h->lattice;
+        expect.dtype = h->dtype;
+        expect.K = h->K;
+        expect.nbox = h->nbox;
+        expect.nsites = h->nsites;
+        expect.geometry_hash = geometry_hash(h);
+        expect.payload_bytes = need - sizeof(CkptHeader);
+        std::string why;
+        if (!check_checkpoint(buf, bytes, expect, &why)) return fail(LBM_EINVAL, "%s", why.c_str());
         CkptHeader hd;
         std::memcpy(&hd, buf, sizeof(hd));
-        if (hd.magic != kCkptMagic) return fail(LBM_EINVAL, "not a checkpoint written by lbm_get_state");
-        if (hd.lattice != h->lattice || hd.dtype != h->dtype || hd.K != h->K || hd.nbox != h->nbox ||
-            hd.nsites != h->nsites || hd.geometry_hash != geometry_hash(h) || hd.payload_bytes != need - sizeof(hd))
-            return fail(LBM_EINVAL, "checkpoint does not match this handle (lattice, dtype, K or geometry)");
         HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
         if (lbm_status st = ensure_buffers(h)) return st;
         if (lbm_status st = build_tiles(h)) return st;

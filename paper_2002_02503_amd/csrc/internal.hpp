@@ -1,5 +1,5 @@
 // Library-internal declarations shared by the C-ABI implementation and the
-// kernel launchers.
+// kernel launchers (the host-only ones are in host.hpp).
 //
 // Population layout ("blocked structure of arrays", BoxDesc).  The local
 // sites of a box, x fastest, are cut into blocks of w consecutive sites; a
@@ -17,6 +17,8 @@
 #include <cstdint>
 #include <string>
 #include <vector>
+
+#include "host.hpp"
 
 namespace lbm {
 
@@ -74,16 +76,6 @@ struct ChunkDesc {
     int box;
 };
 
-// Where a single box's populations are, as the step kernels leave them.
-//   kNatural:   population i of site x in its own row tile, tile row m(i)
-//               (every batch, and the two-buffer single-box steps);
-//   kSwapped:   at site x + c_i, tile row m(opp(i)) (k_step_ip after an odd
-//               number of its steps);
-//   kTwistEven: at site x + b_i, b_i the positive part of c_i, tile row m(i)
-//               (k_step_tw after an even number of its steps);
-//   kTwistOdd:  at site x + b_i, tile row m(opp(i)) (k_step_tw, odd).
-enum StateLayout : int { kNatural = 0, kSwapped = 1, kTwistEven = 2, kTwistOdd = 3 };
-
 // Kernel launchers (kernels.hip).  All return hipSuccess or the first error.
 // layout: kNatural, or kTwistEven for a single box stepped by k_step_tw.
 hipError_t launch_init(int lat, int dtype, int K, int layout, const double* rho, const double* u, void* dst,
@@ -129,17 +121,5 @@ hipError_t launch_residual(int lat, int dtype, const void* src, int layout, cons
                            const double* u_ref, const ChunkDesc* chunks, int nchunks, const BoxDesc* boxes,
                            long long nsites, double* partial, double* out, bool sqrt_l2, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
-
-// Host copy of a lattice's tables (from the compile-time descriptors).
-struct LatticeInfo {
-    int D, Q, two_n, k_default, k_max, R;
-    double T0;
-    std::vector<int> c;     // Q * 3
-    std::vector<double> w;  // Q
-    std::vector<int> mrow;  // Q: tile row m(i) of population i
-};
-bool lattice_info(int lat, LatticeInfo* out);
-
-size_t storage_bytes(int dtype);
 
 }  // namespace lbm

@@ -516,50 +516,4 @@ hipError_t launch_step_batch(int lat, int dtype, int K, int kind, const void* sr
     });
 }
 
-// ---------------------------------------------------------------------------
-// Host copies of the descriptors.
-// ---------------------------------------------------------------------------
-
-template <class L>
-static void fill_info(LatticeInfo* out)
-{
-    out->D = L::D;
-    out->Q = L::Q;
-    out->two_n = L::TWO_N;
-    out->k_default = L::K_DEFAULT;
-    out->k_max = L::K_MAX;
-    out->R = L::R;
-    out->T0 = L::T0;
-    out->c.resize(L::Q * 3);
-    out->w.resize(L::Q);
-    out->mrow.resize(L::Q);
-    for (int i = 0; i < L::Q; ++i) {
-        for (int a = 0; a < 3; ++a) out->c[i * 3 + a] = L::c[i][a];
-        out->w[i] = L::w[i];
-        out->mrow[i] = mem_row<L>(i);
-    }
-}
-
-bool lattice_info(int lat, LatticeInfo* out)
-{
-    switch (lat) {
-    case kD2Q9: fill_info<D2Q9>(out); return true;
-    case kD3Q15: fill_info<D3Q15>(out); return true;
-    case kD3Q19: fill_info<D3Q19>(out); return true;
-    case kD3Q39: fill_info<D3Q39>(out); return true;
-    default: return false;
-    }
-}
-
-size_t storage_bytes(int dtype)
-{
-    switch (dtype) {
-    case 0: return 8;
-    case 1: return 4;
-    case 2: return 2;
-    case 3: return 2;
-    default: return 0;
-    }
-}
-
 }  // namespace lbm
