@@ -248,40 +248,54 @@ def test_size_limits_are_refused_before_allocation():
             assert sim.info()["nsites"] == dims[0] * dims[1] * dims[2]
 
 
-def test_box_of_more_than_2_31_sites():
+@pytest.mark.parametrize("kernel", ["in_place", "twist"])
+def test_box_of_more_than_2_31_sites(kernel):
     """A single D3Q19 box of 2^31 + 2^20 sites (1024 x 1024 x 2049), FP16, in
-    place (82 GB of populations, fields on the device): a shear wave along x
-    stays x-only bit for bit and equals the 1024 x 1 x 1 box's run."""
+    place (82 GB of populations, fields on the device).  The field varies
+    along x and z (u_x along z, u_y along x), so a site index that wrapped at
+    32 bits would land on a site with other values: after the steps the field
+    is y-independent bit for bit and equals the 1024 x 1 x 2049 box's run, and
+    the FP64 totals are ny times that box's."""
     import torch
 
     from paper_2002_02503_amd import lbm
 
     nx, ny, nz = 1024, 1024, 2049
     U, tau, steps = (0.05, 0.02, -0.03), 0.6, 5
-    x = torch.arange(nx, dtype=torch.float64, device="cuda")
-    rho = torch.ones((nz, ny, nx), dtype=torch.float64, device="cuda")
-    u = torch.empty((3, nz, ny, nx), dtype=torch.float64, device="cuda")
-    u[0] = U[0]
-    u[1] = U[1] + 0.01 * torch.sin(2 * torch.pi * x / nx)
-    u[2] = U[2]
-    with lbm.Simulation("D3Q19", (nx, ny, nz), tau, dtype="fp16", kernel="in_place", torch_memory=False) as sim:
+
+    def fields(ny_, dev):
+        lib = torch if dev else np
+        kw = {"dtype": torch.float64, "device": "cuda"} if dev else {}
+        x = lib.arange(nx, **kw) if dev else np.arange(nx, dtype=np.float64)
+        z = lib.arange(nz, **kw) if dev else np.arange(nz, dtype=np.float64)
+        shape = (nz, ny_, nx)
+        rho = torch.ones(shape, **kw) if dev else np.ones(shape)
+        u = torch.empty((3,) + shape, **kw) if dev else np.empty((3,) + shape)
+        u[0] = U[0] + 0.01 * lib.sin(2 * np.pi * z / nz)[:, None, None]
+        u[1] = U[1] + 0.01 * lib.sin(2 * np.pi * x / nx)[None, None, :]
+        u[2] = U[2]
+        return rho, u
+
+    with lbm.Simulation("D3Q19", (nx, ny, nz), tau, dtype="fp16", kernel=kernel, torch_memory=False) as sim:
         assert sim.info()["nsites"] > 2 ** 31
+        rho, u = fields(ny, True)
         sim.init(rho, u)  # synchronises: the fields can go before the outputs are made
-        del rho, u, x
+        del rho, u
         torch.cuda.empty_cache()
         sim.step(steps)
+        tot = sim.totals()[0]
         r, uu = sim.moments(device=True)
-    assert torch.equal(uu, uu[:, :1, :1, :].expand_as(uu))
-    assert torch.equal(r, r[:1, :1, :].expand_as(r))
-    row_u, row_r = uu[:, 0, 0, :].cpu().numpy(), r[0, 0, :].cpu().numpy()
+    assert torch.equal(uu, uu[:, :, :1, :].expand_as(uu))
+    assert torch.equal(r, r[:, :1, :].expand_as(r))
+    slab_u, slab_r = uu[:, :, 0, :].cpu().numpy(), r[:, 0, :].cpu().numpy()
     del r, uu
     torch.cuda.empty_cache()
-    rho1 = np.ones((1, 1, nx))
-    u1 = np.empty((3, 1, 1, nx))
-    u1[0] = U[0]
-    u1[1] = U[1] + 0.01 * np.sin(2 * np.pi * np.arange(nx) / nx)
-    u1[2] = U[2]
-    with lbm.Simulation("D3Q19", (nx, 1, 1), tau, dtype="fp16", kernel="in_place") as one:
+    rho1, u1 = fields(1, False)
+    with lbm.Simulation("D3Q19", (nx, 1, nz), tau, dtype="fp16", kernel=kernel) as one:
         one.init(rho1, u1).step(steps)
+        tot1 = one.totals()[0]
         r1, uu1 = one.moments()
-    assert np.array_equal(row_u, uu1[:, 0, 0, :]) and np.array_equal(row_r, r1[0, 0, :])
+    assert np.array_equal(slab_u, uu1[:, :, 0, :]) and np.array_equal(slab_r, r1[:, 0, :])
+    # the reductions over 2^31 + 2^20 sites: ny copies of the slab's totals
+    assert abs(tot[0] / (ny * tot1[0]) - 1) < 1e-12
+    assert np.all(np.abs(tot[1:] - ny * tot1[1:]) <= 1e-12 * tot[0])
