@@ -46,6 +46,14 @@
 
 namespace lbm {
 
+// a b + c rounded once, in the compute type R.
+template <class R>
+__device__ __forceinline__ R fused(R a, R b, R c)
+{
+    if constexpr (std::is_same<R, float>::value) return __builtin_fmaf(a, b, c);
+    else return __builtin_fma(a, b, c);
+}
+
 // Sparse dot products with compile-time integer coefficients: zero terms are
 // dropped and the sum starts from -0.0, which IEEE addition leaves unchanged,
 // so no "0 + x" or "0 * x" survives into the instruction stream.
@@ -161,9 +169,19 @@ __device__ __forceinline__ void collide_site(R (&G)[L::Q], R omega, R theta)
         if constexpr (cy * cz != 0) syz += R(cy * cz) * sp;
     });
 
-    const R drho = sd / SR;
+    // In single precision 1 / (S rho) is the hardware reciprocal (about one
+    // unit in the last place) and sd / S a product with the rounded 1 / S:
+    // an IEEE division is some ten instructions, and these single-precision
+    // steps are bound by instruction issue at 16-bit storage.
+    R drho, inv_rho_s;  // rho - 1 and 1 / (S rho)
+    if constexpr (std::is_same<R, float>::value) {
+        drho = sd * IS;
+        inv_rho_s = __builtin_amdgcn_rcpf(SR + sd);
+    } else {
+        drho = sd / SR;
+        inv_rho_s = R(1) / (SR + sd);
+    }
     const R rho = R(1) + drho;
-    const R inv_rho_s = R(1) / (SR + sd);  // 1 / (S rho)
     const R ux = jx * inv_rho_s, uy = jy * inv_rho_s;
     const R uz = D3 ? jz * inv_rho_s : R(0);
 
@@ -361,8 +379,11 @@ __device__ __forceinline__ void collide_site(R (&G)[L::Q], R omega, R theta)
                     }
                 }
             }
-            G[i] = Wi * (Xe + Xo);
-            G[i + 1] = Wi * (Xe - Xo);
+            // W (Xe +- Xo) as W Xe +- W Xo: one product and two fused
+            // multiply-adds instead of two sums and two products
+            const R WXo = Wi * Xo;
+            G[i] = fused(Wi, Xe, WXo);
+            G[i + 1] = fused(Wi, Xe, -WXo);
         }
     });
 
