@@ -94,6 +94,9 @@ KERNEL_SYMBOLS = {"scalar": "k_step", "row_wave": "k_step_vec", "in_place": "k_s
 MAX_GRAPH_CHUNK = 4096
 
 
+GRAPH_CHUNK = None  # --graph-chunk: steps per captured graph (None: min(steps, 4096))
+
+
 def measure_box(lattice, dims, tau, dtype, rho, u, steps, warmup, tune=True, **kw):
     """Create, initialise, autotune the launch (outside the timed region, state
     restored), then time `steps` steps, issued as graphs of min(steps, 4096)
@@ -103,7 +106,7 @@ def measure_box(lattice, dims, tau, dtype, rho, u, steps, warmup, tune=True, **k
 
     from paper_2002_02503_amd import lbm
 
-    chunk = min(steps, MAX_GRAPH_CHUNK)
+    chunk = min(steps, MAX_GRAPH_CHUNK) if GRAPH_CHUNK is None else GRAPH_CHUNK
     with lbm.Simulation(lattice, dims, tau, dtype=dtype, graph_chunk=chunk, **kw) as sim:
         t0 = time.perf_counter()
         sim.init(rho, u)  # host fields in, synchronises
@@ -409,6 +412,9 @@ def main():
     ap.add_argument("--no-errors", action="store_true",
                     help="skip the variants' error statements and the Galilean test (oracle on reductions)")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle stepping")
+    ap.add_argument("--graph-chunk", type=int, default=None,
+                    help="steps per captured graph (default min(steps, 4096); 1 = direct launches, as counter "
+                         "collection needs)")
     ap.add_argument("--kernel", choices=["tune", "scalar", "row_wave", "in_place", "two_row", "twist"],
                     default="tune",
                     help="headline step kernel: autotuned (default) or pinned")
@@ -420,6 +426,11 @@ def main():
                          "d3q39_192: only the D3Q39 192^3 FP32 shear wave; the last two print their own roofline "
                          "(profiling aids)")
     args = ap.parse_args()
+    global GRAPH_CHUNK
+    if args.graph_chunk is not None:
+        if not 1 <= args.graph_chunk <= MAX_GRAPH_CHUNK:
+            ap.error("--graph-chunk must be in [1, 4096]")
+        GRAPH_CHUNK = args.graph_chunk
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the slab decomposition over xGMI is a design, not code). Run with --gpus 1.", file=sys.stderr)
