@@ -42,7 +42,7 @@ def traffic_file(kernel: str, workload: str = "turbulence256", dtype: str = "fp3
     """Committed counter summary of the step for one kernel variant, on the
     headline box (in one storage type), the 256-box batch or the D3Q39 box."""
     if workload == "batch256":
-        return os.path.join(ROOT, "profiles", "traffic_batch256_fp32.json")
+        return os.path.join(ROOT, "profiles", f"traffic_batch256_{dtype}.json")
     if workload == "d3q39_192":
         return os.path.join(ROOT, "profiles", f"traffic_d3q39_192_fp32_{kernel}.json")
     return os.path.join(ROOT, "profiles", f"traffic_d3q19_256_{dtype}_{kernel}.json")
@@ -345,29 +345,34 @@ def variant_error_leg():
     from paper_2002_02503_amd import inputs, lbm
 
     out = {}
-    log("error statement: 256-box batch, 1000 steps, 16 boxes against the oracle")
+    log("error statement: 256-box batch (FP32, FP16), 1000 steps, 16 boxes against the oracle")
     boxes = inputs.batch_boxes()
     dims, taus, rho, u = batch_fields()
-    with lbm.Simulation("D3Q19", dims, taus, dtype="fp32", graph_chunk=1000) as sim:
-        sim.init(rho, u).step(1000)
-        r, uu = sim.moments()
-        rb, ub = sim.split_boxes(r), sim.split_boxes(uu)
+    fields = {}
+    for dt in ["fp32", "fp16"]:
+        with lbm.Simulation("D3Q19", dims, taus, dtype=dt, graph_chunk=1000) as sim:
+            sim.init(rho, u).step(1000)
+            r, uu = sim.moments()
+            fields[dt] = (sim.split_boxes(r), sim.split_boxes(uu))
     del rho, u
-    worst = {}
+    worst = {"fp32": {}, "fp16": {}}
     for k in range(0, len(boxes), 16):
         nx, ny, _ = boxes[k]["dims"]
         r1, u1 = inputs.taylor_green_box((nx, ny, 1), boxes[k]["U"], 1.0 / 3.0)
         ref = oracle.Sim("D3Q19", (nx, ny, 1), boxes[k]["tau"], mode="closed").init(r1, u1).step(1000)
         r_ref, u_ref = ref.moments()
-        e = err_norms(rb[k][:1], ub[k][:, :1], r_ref, u_ref)
-        # most vortices have decayed to round-off by t = 1000: relate the
-        # error to the initial vortex amplitude instead of the final one
-        Ub = np.asarray(boxes[k]["U"]).reshape(3, 1, 1, 1)
-        e["u_max_rel_to_initial_wave"] = float(np.abs(ub[k][:, :1] - u_ref).max() / np.abs(u1 - Ub).max())
-        for key, v in e.items():
-            worst[key] = max(worst.get(key, 0.0), v)
-    out["batched_fp32"] = dict(worst, horizon_steps=1000, note="worst of boxes 0, 16, ..., 240 (per-box norms) "
-                                                                "against their nx x ny x 1 oracle runs")
+        for dt, (rb, ub) in fields.items():
+            e = err_norms(rb[k][:1], ub[k][:, :1], r_ref, u_ref)
+            # most vortices have decayed to round-off by t = 1000: relate the
+            # error to the initial vortex amplitude instead of the final one
+            Ub = np.asarray(boxes[k]["U"]).reshape(3, 1, 1, 1)
+            e["u_max_rel_to_initial_wave"] = float(np.abs(ub[k][:, :1] - u_ref).max() / np.abs(u1 - Ub).max())
+            for key, v in e.items():
+                worst[dt][key] = max(worst[dt].get(key, 0.0), v)
+    for dt in ["fp32", "fp16"]:
+        out[f"batched_{dt}"] = dict(worst[dt], horizon_steps=1000, bound=lbm.STATED_BOUNDS[dt],
+                                    note="worst of boxes 0, 16, ..., 240 (per-box norms) against their "
+                                         "nx x ny x 1 oracle runs")
     log("error statement: D3Q39 192^3 K = 5, 300 steps")
     U = (0.2, 0.0, 0.0)
     srho, su = inputs.shear_wave((192, 192, 192), 0.01, U)
@@ -420,7 +425,8 @@ def main():
                     help="headline step kernel: autotuned (default) or pinned")
     ap.add_argument("--block", type=int, default=256, help="threads per block when --kernel is pinned")
     ap.add_argument("--dtype", choices=["fp32", "fp16", "bf16"], default="fp32",
-                    help="storage type of the headline box (fp32 is the headline; the others are profiling aids)")
+                    help="storage type of the headline box or of --workload batch256 (fp32 is the headline; the others "
+                         "are profiling aids)")
     ap.add_argument("--workload", choices=["turbulence256", "batch256", "d3q39_192"], default="turbulence256",
                     help="turbulence256: the headline box (default); batch256: only the 256-box FP32 batch; "
                          "d3q39_192: only the D3Q39 192^3 FP32 shear wave; the last two print their own roofline "
@@ -486,6 +492,9 @@ def main():
         bdims, btaus, brho, bu = batch_fields()
         variants["batched_fp32"] = measure_box("D3Q19", bdims, btaus, "fp32", brho, bu, 1000, args.warmup)
         variants["batched_fp32"]["config"] = "256 boxes, sides 16..64, tau 0.52..1, |U| <= 0.1, Taylor-Green"
+        log("batched: 256 D3Q19 boxes in FP16 storage, 1000 steps")
+        variants["batched_fp16"] = measure_box("D3Q19", bdims, btaus, "fp16", brho, bu, 1000, args.warmup)
+        variants["batched_fp16"]["config"] = variants["batched_fp32"]["config"] + ", FP16 storage of S(f_i - w_i)"
         del brho, bu
         log("D3Q39 192^3 FP32, 1000 steps")
         srho, su = inputs.shear_wave((192, 192, 192), 0.01, (0.2, 0.0, 0.0))
@@ -510,7 +519,8 @@ def main():
 
     # measured HBM traffic of the variants whose launch has a committed counter summary
     for name, wl, dt in [("fp16", "turbulence256", "fp16"), ("bf16", "turbulence256", "bf16"),
-                         ("batched_fp32", "batch256", "fp32"), ("d3q39_fp32_192", "d3q39_192", "fp32")]:
+                         ("batched_fp32", "batch256", "fp32"), ("batched_fp16", "batch256", "fp16"),
+                         ("d3q39_fp32_192", "d3q39_192", "fp32")]:
         if name in variants:
             v = variants[name]
             tb, src = traffic_per_launch(v["kernel"], wl, dt)
@@ -586,28 +596,29 @@ def batch_only(args):
     from paper_2002_02503_amd import lbm
 
     dims, taus, rho, u = batch_fields()
-    log(f"batched FP32, 256 boxes: {args.warmup} warm-up + {args.steps} timed steps")
+    dt = args.dtype
+    log(f"batched {dt.upper()}, 256 boxes: {args.warmup} warm-up + {args.steps} timed steps")
     if args.kernel == "tune":
-        m = measure_box("D3Q19", dims, taus, "fp32", rho, u, args.steps, args.warmup)
+        m = measure_box("D3Q19", dims, taus, dt, rho, u, args.steps, args.warmup)
     elif args.kernel == "scalar":
-        m = measure_box("D3Q19", dims, taus, "fp32", rho, u, args.steps, args.warmup, tune=False, block=args.block)
+        m = measure_box("D3Q19", dims, taus, dt, rho, u, args.steps, args.warmup, tune=False, block=args.block)
     else:
         raise SystemExit("a batch runs the batched kernel: --kernel tune or scalar (block pinned)")
     nsites = m["nsites"]
-    traffic, traffic_src = traffic_per_launch(m["kernel"], "batch256")
+    traffic, traffic_src = traffic_per_launch(m["kernel"], "batch256", dt)
     roofline = {"bound": "hbm", "achieved": m["achieved_GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": m["achieved_GBs"] / PEAK_HBM_GBS, "traffic": traffic,
                 "algorithmic_bytes_per_launch": m["bytes_per_site_update"] * nsites,
-                "kernel": "k_step_batch<D3Q19, float, K=3>", "launch": {"kernel": m["kernel"], "block": m["block"]},
+                "kernel": "k_step_batch<D3Q19, " + {"fp32": "float", "fp16": "_Float16", "bf16": "bf16_t"}[dt] + ", K=3>", "launch": {"kernel": m["kernel"], "block": m["block"]},
                 "traffic_source": traffic_src}
     copy_bytes = m["bytes_per_site_update"] // 2 * nsites
     copy_ms = lbm.copy_probe(copy_bytes, reps=10)
     copy_gbs = 2 * copy_bytes / (copy_ms * 1e-3) / 1e9
-    line = {"metric": "MLUPS & % HBM roofline, 256-box D3Q19 batch FP32", "value": m["value"], "unit": "MLUPS",
+    line = {"metric": f"MLUPS & % HBM roofline, 256-box D3Q19 batch {dt.upper()}", "value": m["value"], "unit": "MLUPS",
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": m["ms_per_step"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "256 D3Q19 boxes, sides 16..64, tau 0.52..1, |U| <= 0.1, Taylor-Green, "
-                                   "FP32 storage, Hermite order 3, one launch per step", "nsites": nsites},
+                                   f"{dt.upper()} storage, Hermite order 3, one launch per step", "nsites": nsites},
             "roofline": roofline, "conservation": m["conservation"], "cpu_baseline": None,
             "copy_probe": {"bytes_moved": 2 * copy_bytes, "GB_s": copy_gbs, "frac_of_peak": copy_gbs / PEAK_HBM_GBS},
             "frac_of_copy": m["achieved_GBs"] / copy_gbs}

@@ -100,6 +100,27 @@ def test_d3q19_shear_wave_128_fp32():
     assert gal["bgk3"] < 1e-3
 
 
+@pytest.mark.parametrize("dtype", ["fp16", "bf16"])
+def test_d3q19_shear_wave_128_16bit(dtype):
+    """The 128^3 shear wave on U = (0.1, 0.05, 0), tau = 0.55, 2000 steps, in
+    16-bit storage against the oracle's 128 x 1 x 1 run: within the stated
+    bound (max |du| over max |u|); also states the error against the wave
+    itself, max |du| over max |u_ref - U|."""
+    n, tau, steps, U = 128, 0.55, 2000, (0.1, 0.05, 0.0)
+    rho, u = inputs.shear_wave((n, n, n), 0.01, U)
+    with lbm.Simulation("D3Q19", (n, n, n), tau, dtype=dtype) as sim:
+        sim.init(rho, u).step(steps)
+        r, uu = sim.moments()
+    rho1, u1 = inputs.shear_wave((n, 1, 1), 0.01, U)
+    r_ref, u_ref = run_oracle("D3Q19", (n, 1, 1), tau, rho1, u1, steps, mode="closed")
+    du = np.abs(uu - u_ref).max()
+    wave = np.abs(u_ref - np.asarray(U).reshape(3, 1, 1, 1)).max()
+    eu, er = rel_u(uu, np.broadcast_to(u_ref, uu.shape)), rel_rho(r, np.broadcast_to(r_ref, r.shape))
+    print(f"D3Q19 128^3 shear {dtype}, 2000 steps: u {eu:.2e} (to the wave {du / wave:.2e}) rho {er:.2e}",
+          flush=True)
+    assert eu < BOUND[dtype] and er < BOUND[dtype]
+
+
 def test_d3q19_galilean_128_fp64():
     """The Galilean test of the shear wave on U = (0.1, 0.05, 0) at 128^3 in
     FP64, where rounding no longer limits the rate fit: the paper's operator
