@@ -15,6 +15,14 @@ def test_bench_refuses_several_gpus():
     assert r.stdout == ""
 
 
+def test_bench_rejects_a_graph_chunk_out_of_range():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--graph-chunk", "0"], cwd=ROOT,
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "--graph-chunk" in r.stderr
+    assert r.stdout == ""
+
+
 def test_bench_help_lists_the_workloads():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"], cwd=ROOT,
                        capture_output=True, text=True, timeout=120)

@@ -348,14 +348,14 @@ def test_batched_256_boxes_fp32():
         assert np.array_equal(u1, ub[k]) and np.array_equal(r1, rb[k]), k
 
 
-def _progress(msg: str) -> None:
-    """A progress line that bypasses pytest's capture (long host-side runs)."""
-    import sys
+def _progress(capfd, msg: str) -> None:
+    """A progress line written past pytest's output capture, so that a long
+    host-side run keeps printing while it works."""
+    with capfd.disabled():
+        print(msg, flush=True)
 
-    print(msg, file=sys.__stderr__, flush=True)
 
-
-def test_turbulence_256_full_horizon_error(turbulence_256):
+def test_turbulence_256_full_horizon_error(turbulence_256, capfd):
     """The headline workload at its own configuration: D3Q19, 256^3, tau =
     0.51, decaying turbulence, 500 steps, every storage type against the
     oracle's full 256^3 run (closed mode, pinned equal to the literal mode, on
@@ -370,11 +370,11 @@ def test_turbulence_256_full_horizon_error(turbulence_256):
         with lbm.Simulation("D3Q19", (256, 256, 256), tau, dtype=dtype) as sim:
             sim.init(rho, u).step(steps)
             got[dtype] = sim.moments()
-        _progress(f"full-horizon error: GPU {dtype} 500 steps done")
+        _progress(capfd, f"full-horizon error: GPU {dtype} 500 steps done")
     sim = oracle.Sim("D3Q19", (256, 256, 256), tau, mode="closed").init(rho, u)
     for t in range(every, steps + 1, every):
         sim.step(every)
-        _progress(f"full-horizon error: oracle at step {t} of {steps} ({oracle.get_threads()} threads)")
+        _progress(capfd, f"full-horizon error: oracle at step {t} of {steps} ({oracle.get_threads()} threads)")
     r_ref, u_ref = sim.moments()
     del sim
     umax = np.abs(u_ref).max()
@@ -388,7 +388,7 @@ def test_turbulence_256_full_horizon_error(turbulence_256):
              "rho_max": float(np.abs(dr).max()), "rho_l2": float(np.sqrt(np.sum(dr * dr)) / r_l2)}
         print(f"FULL HORIZON 256^3 500 steps {dtype}: u max {e['u_max']:.3e} u L2 {e['u_l2']:.3e} "
               f"rho max {e['rho_max']:.3e} rho L2 {e['rho_l2']:.3e} (bound {BOUND[dtype]:g})", flush=True)
-        _progress(f"full-horizon error {dtype}: {e}")
+        _progress(capfd, f"full-horizon error {dtype}: {e}")
         if not (e["u_max"] < BOUND[dtype] and e["rho_max"] < BOUND[dtype]):
             bad.append(dtype)
     assert not bad, bad
