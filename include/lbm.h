@@ -77,10 +77,14 @@ typedef enum {
                                  results, half the memory) */
     LBM_KERNEL_TWO_ROW = 4,   /* two sites per thread (rows 2j and 2j+1, ny even): the second site's loads
                                  are in flight while the first collides (bit-identical results) */
-    LBM_KERNEL_TWIST = 5      /* in place on one buffer with the twisted layouts: every step reads and
+    LBM_KERNEL_TWIST = 5,     /* in place on one buffer with the twisted layouts: every step reads and
                                  writes each element once, only at the cells x + b (b the positive part
                                  of a velocity), so it touches fewer row tiles (bit-identical results,
                                  half the memory) */
+    LBM_KERNEL_TWO_STEP = 6   /* two steps per launch (D3Q15, D3Q19): a block walks a column of the box
+                                 in z, takes the first step on the column and a one-site ring around it
+                                 and keeps that state in LDS for the second, so the state is read and
+                                 written once per two steps (bit-identical results) */
 } lbm_kernel;
 
 typedef struct {
@@ -185,7 +189,9 @@ lbm_status lbm_set_graph_chunk(lbm_t h, int32_t steps);
 /* Launch shape: threads per block (64, 128 or 256; 0 = default) and,
  * for batches, the number of blocks of the persistent step kernel (0 = enough
  * blocks for every tile to get its own wave; a batch tile is one wave's work:
- * one 64-site block of a box's layout).  Only before lbm_init. */
+ * one 64-site block of a box's layout).  For a single box the grid is the
+ * number of blocks of LBM_KERNEL_TWO_STEP (0 = one per compute unit; its
+ * blocks have a fixed size).  Only before lbm_init. */
 lbm_status lbm_set_launch(lbm_t h, int32_t block, int32_t grid);
 
 /* Choose the single-box step kernel.  All variants compute the same bits.
@@ -208,6 +214,10 @@ lbm_status lbm_set_launch(lbm_t h, int32_t block, int32_t grid);
  * lbm_set_state write that layout; the readers and lbm_get_state handle it as
  * they handle the swapped one.
  * LBM_KERNEL_TWO_ROW needs a single box with ny even (else LBM_EINVAL).
+ * LBM_KERNEL_TWO_STEP needs a single D3Q15 or D3Q19 box with nx a multiple of
+ * 32, ny a multiple of 16 (8 for FP64 storage) and one z-plane of populations
+ * (Q nx ny values) below 2 GiB, else LBM_EINVAL.  An odd step count ends with
+ * one step of the scalar kernel; the state stays in the natural layout.
  * May be called at any time: on an initialised handle the state is first
  * brought to the natural layout and then into the new kernel's starting
  * layout (which may allocate the second buffer), and the run continues bit
@@ -219,7 +229,8 @@ lbm_status lbm_set_kernel(lbm_t h, int32_t kernel);
  * round.  Single box: the scalar step at 64/128/256 threads per block, the
  * in-place, twist and two-row (ny even) steps at 256, the scalar, in-place
  * and twist steps at one whole x-row per block when nx rounds up to 192 lanes,
- * and the row-wave step where it applies.  Batch: 64/128/256 threads per block, with
+ * the row-wave step where it applies, and the two-step kernel (where it
+ * applies) at one and at two blocks per compute unit.  Batch: 64/128/256 threads per block, with
  * one wave per 64-site block of the layout or 1024/2048/4096 persistent
  * blocks.  The state is saved before and restored after, so t and the
  * populations are unchanged (all candidates compute the same bits).  Choices are appended to the text file `cache_path` (NULL: the

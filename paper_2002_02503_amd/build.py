@@ -29,6 +29,9 @@ STORAGE = ["double", "float", "_Float16", "bf16_t"]
 # units compile in parallel in similar times.
 INSTANCE_GROUPS = ([("D2Q9", STORAGE), ("D3Q15", STORAGE), ("D3Q19", STORAGE)]
                    + [("D3Q39", [s]) for s in STORAGE])
+# Two-step kernel instances (lattices with a one-site ring), one unit per
+# (lattice, storage type): each instance holds two collisions.
+STEP2_GROUPS = [(lat, [s]) for lat in ("D3Q15", "D3Q19") for s in STORAGE]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -51,13 +54,16 @@ def _compile(src: str, obj: str) -> None:
 
 def _instance_units(gendir: str) -> list:
     """Write the step-kernel instance units: each includes step.hpp (single
-    box) or step_batch.hpp (batch) and instantiates the launchers of one group
-    of (lattice, storage type) pairs."""
+    box), step_batch.hpp (batch) or step2.hpp (two steps per launch) and
+    instantiates the launchers of one group of (lattice, storage type)
+    pairs."""
     units = []
-    for lat, types in INSTANCE_GROUPS:
-        tag = lat.lower() + ("" if len(types) > 1 else "_" + types[0].strip("_").lower())
-        for family, header, macro in [("step", "step.hpp", "LBM_DECLARE_STEP_INSTANCES"),
-                                      ("batch", "step_batch.hpp", "LBM_DECLARE_BATCH_INSTANCES")]:
+    families = [("step", "step.hpp", "LBM_DECLARE_STEP_INSTANCES", INSTANCE_GROUPS),
+                ("batch", "step_batch.hpp", "LBM_DECLARE_BATCH_INSTANCES", INSTANCE_GROUPS),
+                ("step2", "step2.hpp", "LBM_DECLARE_STEP2_INSTANCES", STEP2_GROUPS)]
+    for family, header, macro, groups in families:
+        for lat, types in groups:
+            tag = lat.lower() + ("" if len(types) > 1 else "_" + types[0].strip("_").lower())
             path = os.path.join(gendir, f"{family}_{tag}.hip")
             lines = [f"// {family} kernels of {lat} ({', '.join(types)}); written by build.py",
                      f'#include "{header}"', "namespace lbm {"]

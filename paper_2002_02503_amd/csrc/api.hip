@@ -98,6 +98,7 @@ struct lbm_ctx {
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
     int device = 0;
+    int cus = 1;                    // compute units of the device
     int block = 0;                  // 0 = automatic
     int grid = 0;                   // batched: 0 = one block per tile
     int kernel = LBM_KERNEL_AUTO;   // single box: scalar or row-wave step
@@ -287,6 +288,9 @@ lbm_status create_common(lbm_t* out, int32_t lattice, int32_t nbox, const int64_
         h->offset.resize(nbox);
         h->mem.resize(nbox);
         h->device = dev;
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            h->cus = cus;
         // A single box is stored in row tiles (blocks of w = nx sites); the boxes
         // of a batch in blocks of 64 sites, each box padded to whole blocks.
         int64_t off = 0, stored = 0;
@@ -397,6 +401,18 @@ bool twisted(const lbm_ctx* h) { return is_single(h) && effective_kernel(h) == L
 // The step works inside one buffer (either in-place form).
 bool one_buffer(const lbm_ctx* h) { return in_place(h) || twisted(h); }
 
+// The two-step kernel applies to this box (host.hpp, two_step_fits) / is the
+// one in use.
+bool two_step_ok(const lbm_ctx* h)
+{
+    return is_single(h) && two_step_fits(h->lat, h->dtype, h->dims[0], h->dims[1], h->dims[2]);
+}
+bool two_step(const lbm_ctx* h) { return is_single(h) && effective_kernel(h) == LBM_KERNEL_TWO_STEP; }
+
+// Blocks of the two-step kernel: the chosen grid, else one per compute unit
+// (its LDS planes leave room for one block per CU; measured fastest).
+int two_step_grid(const lbm_ctx* h) { return h->grid > 0 ? h->grid : h->cus; }
+
 // Layout of the current state (StateLayout): the in-place forms alternate
 // two layouts, h->cur being the parity of the steps they took.
 int state_layout(const lbm_ctx* h)
@@ -462,6 +478,36 @@ hipError_t launch_one(lbm_ctx* h, int parity, hipStream_t s)
     return launch_step_batch(h->lattice, h->dtype, h->K, step_kind(h), src, dst, h->d_tiles, h->ntiles, h->theta,
                              block, h->grid, h->aligned_rows, s);
 }
+
+// Two steps in one launch (step2.hpp), from buf[parity] into buf[parity ^ 1]:
+// like launch_one for the buffers, two steps for the time.
+hipError_t launch_two(lbm_ctx* h, int parity, hipStream_t s)
+{
+    Step2Geom geo;
+    geo.nx = int(h->dims[0]);
+    geo.ny = int(h->dims[1]);
+    geo.nz = int(h->dims[2]);
+    geo.ncx = int(h->dims[0] / kTwoStepTileX);
+    const long long ncy = h->dims[1] / two_step_tile_y(h->elem);
+    geo.total = (long long)geo.ncx * ncy * geo.nz;
+    const int grid = two_step_grid(h);
+    geo.per = (geo.total + grid - 1) / grid;
+    geo.xcd_order = (grid % 8 == 0) ? 1 : 0;
+    return launch_step2(h->lattice, h->dtype, h->K, step_kind(h), h->buf[parity], h->buf[parity ^ 1], geo,
+                        1.0 - 1.0 / h->tau[0], h->theta, grid, s);
+}
+
+// Steps the next launch takes when `left` remain: two for the two-step kernel
+// (an odd last step goes to the one-site step), else one.
+int steps_in_launch(const lbm_ctx* h, int64_t left) { return (two_step(h) && left >= 2) ? 2 : 1; }
+
+hipError_t launch_steps(lbm_ctx* h, int parity, int k, hipStream_t s)
+{
+    return k == 2 ? launch_two(h, parity, s) : launch_one(h, parity, s);
+}
+
+// Launches that take n steps; each flips the buffer parity.
+int64_t launches_for(const lbm_ctx* h, int64_t n) { return two_step(h) ? n / 2 + n % 2 : n; }
 
 // Where the current state is, and in which layout (StateLayout).
 void state_view(const lbm_ctx* h, const void** state, int* layout)
@@ -532,7 +578,12 @@ lbm_status build_graph(lbm_ctx* h, int parity)
     if (st != LBM_OK) return st;
     HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
     hipError_t le = hipSuccess;
-    for (int k = 0; k < n && le == hipSuccess; ++k) le = launch_one(h, parity ^ (k & 1), h->cap_stream);
+    int p = parity;
+    for (int left = n; left > 0 && le == hipSuccess; p ^= 1) {
+        const int k = steps_in_launch(h, left);
+        le = launch_steps(h, p, k, h->cap_stream);
+        left -= k;
+    }
     hipGraph_t graph = nullptr;
     hipError_t ee = hipStreamEndCapture(h->cap_stream, &graph);
     if (le != hipSuccess) {
@@ -723,8 +774,14 @@ lbm_status lbm_set_kernel(lbm_t h, int32_t kernel)
     try {
         if (lbm_status st = check_handle(h)) return st;
         if (kernel != LBM_KERNEL_AUTO && kernel != LBM_KERNEL_SCALAR && kernel != LBM_KERNEL_ROW_WAVE &&
-            kernel != LBM_KERNEL_IN_PLACE && kernel != LBM_KERNEL_TWO_ROW && kernel != LBM_KERNEL_TWIST)
+            kernel != LBM_KERNEL_IN_PLACE && kernel != LBM_KERNEL_TWO_ROW && kernel != LBM_KERNEL_TWIST &&
+            kernel != LBM_KERNEL_TWO_STEP)
             return fail(LBM_EINVAL, "unknown kernel variant %d", kernel);
+        if (kernel == LBM_KERNEL_TWO_STEP && !two_step_ok(h))
+            return fail(LBM_EINVAL,
+                        "the two-step kernel needs a single D3Q15 or D3Q19 box with nx a multiple of %d, ny a "
+                        "multiple of %d and one z-plane of populations below 2 GiB",
+                        kTwoStepTileX, two_step_tile_y(h->elem));
         if ((kernel == LBM_KERNEL_IN_PLACE || kernel == LBM_KERNEL_TWIST) && !is_single(h))
             return fail(LBM_EINVAL, "the in-place steps are for a single box; batches use the tiled batched kernel");
         if (kernel == LBM_KERNEL_TWO_ROW && (!is_single(h) || h->dims[1] % 2 != 0))
@@ -816,16 +873,18 @@ lbm_status lbm_step(lbm_t h, int64_t n)
             while (left >= G) {
                 if (lbm_status st = build_graph(h, h->cur)) return st;
                 HIP_TRY(hipGraphLaunch(h->gexec[h->cur], h->stream), "hipGraphLaunch");
-                h->cur ^= (G & 1);
+                h->cur ^= int(launches_for(h, G) & 1);
                 h->t += G;
                 left -= G;
             }
         }
-        for (; left > 0; --left) {
-            hipError_t e = launch_one(h, h->cur, h->stream);
+        while (left > 0) {
+            const int k = steps_in_launch(h, left);
+            hipError_t e = launch_steps(h, h->cur, k, h->stream);
             if (e != hipSuccess) return fail_hip(e, "step kernel launch");
             h->cur ^= 1;
-            h->t += 1;
+            h->t += k;
+            left -= k;
         }
         return LBM_OK;
     } catch (const std::bad_alloc&) {
@@ -876,7 +935,8 @@ lbm_status lbm_tune(lbm_t h, int32_t steps, const char* cache_path)
         LaunchChoice best;
         if (tune_cache_lookup(cache_path, key, &best)) {
             // the cache is a text file: take only values this library can launch
-            if (best.kernel < LBM_KERNEL_AUTO || best.kernel > LBM_KERNEL_TWIST) best.kernel = LBM_KERNEL_SCALAR;
+            if (best.kernel < LBM_KERNEL_AUTO || best.kernel > LBM_KERNEL_TWO_STEP) best.kernel = LBM_KERNEL_SCALAR;
+            if (best.kernel == LBM_KERNEL_TWO_STEP && !two_step_ok(h)) best.kernel = LBM_KERNEL_SCALAR;
             if (!(best.block == 0 || (best.block >= 64 && best.block <= 256 && best.block % 64 == 0))) best.block = 0;
             if (best.grid < 0) best.grid = 0;
             if (best.kernel == LBM_KERNEL_ROW_WAVE && !row_wave_sites(h)) best.kernel = LBM_KERNEL_SCALAR;
@@ -904,6 +964,11 @@ lbm_status lbm_tune(lbm_t h, int32_t steps, const char* cache_path)
             }
             if (h->dims[1] % 2 == 0) cand.push_back({LBM_KERNEL_TWO_ROW, 256, 0});
             if (row_wave_sites(h)) cand.push_back({LBM_KERNEL_ROW_WAVE, 0, 0});
+            // the two-step kernel at one and two blocks per compute unit
+            if (two_step_ok(h)) {
+                cand.push_back({LBM_KERNEL_TWO_STEP, 0, 0});
+                cand.push_back({LBM_KERNEL_TWO_STEP, 0, 2 * h->cus});
+            }
         } else {
             for (int b : {64, 128, 256})
                 for (int g : {0, 1024, 2048, 4096}) cand.push_back({LBM_KERNEL_SCALAR, b, g});
@@ -1246,7 +1311,7 @@ lbm_status lbm_get_info(lbm_t h, lbm_info* info)
         info->bytes_per_site_update = int64_t(2 * h->lat.Q) * int64_t(h->elem);
         info->state_bytes = h->state_bytes;
         info->block = effective_block(h);
-        info->grid = h->grid;
+        info->grid = two_step(h) ? two_step_grid(h) : h->grid;
         info->graph_chunk = h->graph_chunk;
         info->kernel = effective_kernel(h);
         info->collision = h->collision;

@@ -99,6 +99,16 @@ bool check_boxes(const LatticeInfo& L, int dtype, int nbox, const int64_t* dims,
     return true;
 }
 
+bool two_step_fits(const LatticeInfo& L, int dtype, int64_t nx, int64_t ny, int64_t nz)
+{
+    const size_t elem = storage_bytes(dtype);
+    if (L.D != 3 || L.R != 1 || elem == 0) return false;
+    if (nx < 1 || ny < 1 || nz < 1 || nx > INT32_MAX || ny > INT32_MAX || nz > INT32_MAX) return false;
+    if (nx % kTwoStepTileX != 0 || ny % two_step_tile_y(elem) != 0) return false;
+    const uint64_t plane_sites = uint64_t(nx) * uint64_t(ny);  // below 2^62
+    return plane_sites <= ((uint64_t(1) << 31) - 1) / (uint64_t(L.Q) * elem);
+}
+
 uint64_t geometry_hash(const std::vector<int64_t>& dims)
 {
     uint64_t x = 1469598103934665603ULL;  // FNV-1a over the dims

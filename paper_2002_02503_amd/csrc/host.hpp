@@ -39,6 +39,21 @@ size_t storage_bytes(int dtype);
 constexpr int64_t kMaxSites = int64_t(1) << 36;  // total sites: keeps chunk and tile counts in int
 constexpr int kBlockSites = 64;                  // sites per block of a batched box's layout (one wave)
 
+// Output tile of the two-step kernel (step2.hpp): kTwoStepTileX x
+// two_step_tile_y(elem) sites of a z-plane per block, which also computes the
+// one-site ring around them in its first step.  8-byte storage takes half the
+// rows, so that the kernel's two LDS planes (2 Q (TX + 2)(TY + 2) values)
+// stay within a compute unit's 160 KiB.
+constexpr int kTwoStepTileX = 32;
+constexpr int two_step_tile_y(size_t elem) { return elem == 8 ? 8 : 16; }
+
+// Whether the two-step kernel applies to a single nx x ny x nz box: a 3-D
+// lattice whose velocity components are at most 1 in magnitude (a one-site
+// ring), nx and ny multiples of the tile, and one z-plane of populations
+// (Q nx ny values) below 2 GiB, since offsets inside a plane are formed in
+// 32 bits.
+bool two_step_fits(const LatticeInfo& L, int dtype, int64_t nx, int64_t ny, int64_t nz);
+
 // The argument checks of lbm_create / lbm_create_batch for nbox boxes
 // (dims: nbox * 3, tau: nbox).  True when every box is valid; otherwise false
 // with the reason in *why.

@@ -28,6 +28,18 @@ struct StepGeom {
     int xblocks;          // blocks per x-row
 };
 
+// Single box, two-step kernel (step2.hpp): the (x, y) plane is cut into
+// columns of the output tile, ncx of them along x; column-plane
+// w = column * nz + z, and block b takes the `per` consecutive column-planes
+// from (b or its XCD-ordered index) * per on, `total` of them in all.
+struct Step2Geom {
+    int nx, ny, nz;
+    int ncx;
+    long long total;
+    long long per;
+    int xcd_order;        // 1: consecutive columns on one XCD (grid a multiple of 8)
+};
+
 // Single box, row-wave form: each lane owns V consecutive sites of an x-row,
 // a row takes lanes_per_row = nx / V lanes and a 64-lane wavefront holds
 // rows_per_wave = 64 / lanes_per_row rows.
@@ -94,6 +106,10 @@ hipError_t launch_step_ip(int lat, int dtype, int K, int kind, void* buf, bool f
 // odd one (step.hpp, k_step_tw).
 hipError_t launch_step_tw(int lat, int dtype, int K, int kind, void* buf, bool even, const StepGeom& geo,
                           double omega, double theta, int block, hipStream_t s);
+// Two steps in one launch (step2.hpp, k_step2), from src to dst, on `grid`
+// blocks; D3Q15 and D3Q19 only (two_step_fits), else hipErrorInvalidValue.
+hipError_t launch_step2(int lat, int dtype, int K, int kind, const void* src, void* dst, const Step2Geom& geo,
+                        double omega, double theta, int grid, hipStream_t s);
 // A single box's state from `layout` to the natural layout (to_natural) or
 // back, into another buffer (bit-exact permutation).
 hipError_t launch_relayout(int lat, int dtype, int layout, bool to_natural, const void* src, void* dst,

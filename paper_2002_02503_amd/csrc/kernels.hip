@@ -464,6 +464,19 @@ hipError_t launch_step(int lat, int dtype, int K, int kind, const void* src, voi
     });
 }
 
+hipError_t launch_step2(int lat, int dtype, int K, int kind, const void* src, void* dst, const Step2Geom& geo,
+                        double omega, double theta, int grid, hipStream_t s)
+{
+    return by_pair(lat, dtype, [&](auto Lt, auto* Sp) -> hipError_t {
+        using L = decltype(Lt);
+        using S = std::remove_pointer_t<decltype(Sp)>;
+        if constexpr (std::is_same<L, D3Q15>::value || std::is_same<L, D3Q19>::value)
+            return launch_step2_l<L, S>(K, kind, src, dst, geo, omega, theta, grid, s);
+        else
+            return hipErrorInvalidValue;
+    });
+}
+
 int vec_sites_per_lane(int lat, int dtype)
 {
     int v = 0;

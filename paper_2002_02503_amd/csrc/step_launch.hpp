@@ -31,6 +31,11 @@ template <class L, class S>
 hipError_t launch_step_tw_l(int K, int kind, void* buf, bool even, const StepGeom& geo, double omega, double theta,
                             int block, hipStream_t s);
 
+// Single box, two steps per launch (3-D lattices with a one-site ring only).
+template <class L, class S>
+hipError_t launch_step2_l(int K, int kind, const void* src, void* dst, const Step2Geom& geo, double omega,
+                          double theta, int grid, hipStream_t s);
+
 // Sites per lane of the row-wave form (0: none for this pair).
 template <class L, class S>
 int vec_sites_l();
@@ -57,6 +62,10 @@ hipError_t launch_step_batch_l(int K, int kind, const void* src, void* dst, cons
     EXT template hipError_t launch_step_vec_l<L, S>(int, int, const void*, void*, const VecGeom&, double,      \
                                                     double, hipStream_t);
 
+#define LBM_DECLARE_STEP2_INSTANCES(EXT, L, S)                                                                 \
+    EXT template hipError_t launch_step2_l<L, S>(int, int, const void*, void*, const Step2Geom&, double, double, \
+                                                 int, hipStream_t);
+
 #define LBM_DECLARE_BATCH_INSTANCES(EXT, L, S)                                                                 \
     EXT template hipError_t launch_step_batch_l<L, S>(int, int, const void*, void*, const TileDesc*, int,    \
                                                       double, int, int, bool, hipStream_t);
@@ -71,9 +80,17 @@ hipError_t launch_step_batch_l(int K, int kind, const void* src, void* dst, cons
     LBM_EXTERN_PAIR(L, _Float16)    \
     LBM_EXTERN_PAIR(L, bf16_t)
 
+#define LBM_EXTERN_STEP2(L)                            \
+    LBM_DECLARE_STEP2_INSTANCES(extern, L, double)     \
+    LBM_DECLARE_STEP2_INSTANCES(extern, L, float)      \
+    LBM_DECLARE_STEP2_INSTANCES(extern, L, _Float16)   \
+    LBM_DECLARE_STEP2_INSTANCES(extern, L, bf16_t)
+
 LBM_EXTERN_LATTICE(D2Q9)
 LBM_EXTERN_LATTICE(D3Q15)
 LBM_EXTERN_LATTICE(D3Q19)
 LBM_EXTERN_LATTICE(D3Q39)
+LBM_EXTERN_STEP2(D3Q15)
+LBM_EXTERN_STEP2(D3Q19)
 
 }  // namespace lbm

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 LATTICES = {"D2Q9": 0, "D3Q19": 1, "D3Q39": 2, "D3Q15": 3}
 DTYPES = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
 DTYPE_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2}
-KERNELS = {"auto": 0, "scalar": 1, "row_wave": 2, "in_place": 3, "two_row": 4, "twist": 5}
+KERNELS = {"auto": 0, "scalar": 1, "row_wave": 2, "in_place": 3, "two_row": 4, "twist": 5, "two_step": 6}
 COLLISIONS = {"filtered": 0, "bgk": 1}
 STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE", -4: "LBM_ENODEV",
           -5: "LBM_ESTATE", -6: "LBM_ENUMERIC"}

@@ -2,7 +2,7 @@
 // on synthetic inputs, for a build with AddressSanitizer and
 // UndefinedBehaviorSanitizer (tests/test_host_sanitizers.py): lattice tables,
 // argument checks (every limit, and values at the edges of the integer
-// types), checkpoint header checks (short, foreign and mismatched buffers),
+// types), the two-step kernel's fit rules, checkpoint header checks (short, foreign and mismatched buffers),
 // the layout rearrangement of a state (every lattice and layout, degenerate
 // boxes included, checked to be a permutation that round-trips), and the tune
 // cache (malformed lines).  Any sanitizer report exits non-zero; a failed
@@ -99,6 +99,37 @@ static void test_checks()
     }
     EXPECT(geometry_hash({8, 8, 8}) != geometry_hash({8, 8, 9}));
     EXPECT(geometry_hash({}) == geometry_hash({}));
+}
+
+static void test_two_step_fits()
+{
+    // lattice codes: 0 D2Q9, 1 D3Q19, 2 D3Q39, 3 D3Q15; dtype codes: 0 FP64 .. 3 BF16
+    LatticeInfo q9, q19, q39, q15;
+    lattice_info(0, &q9);
+    lattice_info(1, &q19);
+    lattice_info(2, &q39);
+    lattice_info(3, &q15);
+    const int64_t big = std::numeric_limits<int64_t>::max();
+    for (int dtype = 0; dtype < 4; ++dtype) {
+        EXPECT(two_step_fits(q19, dtype, 256, 256, 256));
+        EXPECT(two_step_fits(q15, dtype, 32, 16, 1));
+        EXPECT(!two_step_fits(q9, dtype, 64, 64, 1));
+        EXPECT(!two_step_fits(q39, dtype, 64, 64, 64));
+        EXPECT(!two_step_fits(q19, dtype, 48, 32, 4));   // nx not a multiple of 32
+        EXPECT(!two_step_fits(q19, dtype, 32, 12, 4));   // ny not a multiple of 8
+        EXPECT(!two_step_fits(q19, dtype, 0, 16, 4));
+        EXPECT(!two_step_fits(q19, dtype, 32, 16, 0));
+        EXPECT(!two_step_fits(q19, dtype, -32, 16, 4));
+        EXPECT(!two_step_fits(q19, dtype, big, big, big));
+        EXPECT(!two_step_fits(q19, dtype, 32, int64_t(1) << 40, 1));
+    }
+    EXPECT(two_step_fits(q19, 0, 32, 24, 3));    // FP64 tile: 32 x 8
+    EXPECT(!two_step_fits(q19, 1, 32, 24, 3));   // FP32 tile: 32 x 16
+    EXPECT(!two_step_fits(q19, 4, 32, 16, 3));   // unknown dtype
+    // one z-plane of populations must stay below 2 GiB: Q nx ny elem < 2^31
+    EXPECT(two_step_fits(q19, 1, 8192, 3440, 1));    // 19 * 8192 * 3440 * 4 = 2141 MB < 2^31
+    EXPECT(!two_step_fits(q19, 1, 8192, 3456, 1));   // 19 * 8192 * 3456 * 4 > 2^31
+    EXPECT(!two_step_fits(q19, 0, 8192, 3440, 1));
 }
 
 static void test_checkpoint()
@@ -217,6 +248,7 @@ int main(int argc, char** argv)
     const char* dir = argc > 1 ? argv[1] : ".";
     test_tables();
     test_checks();
+    test_two_step_fits();
     test_checkpoint();
     test_relayout();
     test_tune_cache(dir);

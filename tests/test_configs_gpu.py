@@ -218,7 +218,7 @@ VARIANT_CASES = [
 ]
 
 
-@pytest.mark.parametrize("kernel", ["scalar", "in_place", "twist"])
+@pytest.mark.parametrize("kernel", ["scalar", "in_place", "twist", "two_step"])
 @pytest.mark.parametrize("lattice,lib_kw,ora_kw", VARIANT_CASES)
 def test_turbulence_256_sampled_parity_variants(turbulence_256, lattice, lib_kw, ora_kw, kernel):
     """The benchmark's other collision kinds and D3Q15 on the full 256^3
@@ -246,8 +246,8 @@ def turbulence_256_samples(turbulence_256):
     return pts, r_ref, u_ref
 
 
-@pytest.mark.parametrize("kernel", ["in_place", "two_row", "twist"])
-@pytest.mark.parametrize("dtype", ["fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("kernel", ["in_place", "two_row", "twist", "two_step"])
+@pytest.mark.parametrize("dtype", ["fp32", "fp16", "bf16", "fp64"])
 def test_turbulence_256_sampled_parity_other_kernels(turbulence_256, turbulence_256_samples, kernel, dtype):
     """The same full-size check for the kernel forms the tuner may pick for the
     benchmark (after 3 steps the in-place state is in its swapped layout)."""
@@ -362,7 +362,8 @@ def test_turbulence_256_full_horizon_error(turbulence_256, capfd):
     all host threads).  States max and L2 errors of u and rho (max |du| over
     max |u|, ||du||_2 over ||u||_2, max |drho|, ||drho||_2 over ||rho||_2) and
     asserts the stated bound of each storage type on the velocity and density
-    maxima."""
+    maxima.  The two-step kernel (which the tuner picks for FP64 and FP32 on
+    this box) gives the same bits over the 500 steps."""
     rho, u = turbulence_256
     tau, steps, every = 0.51, 500, 25
     got = {}
@@ -371,6 +372,12 @@ def test_turbulence_256_full_horizon_error(turbulence_256, capfd):
             sim.init(rho, u).step(steps)
             got[dtype] = sim.moments()
         _progress(capfd, f"full-horizon error: GPU {dtype} 500 steps done")
+        if dtype in ("fp64", "fp32"):
+            with lbm.Simulation("D3Q19", (256, 256, 256), tau, dtype=dtype, kernel="two_step") as sim:
+                sim.init(rho, u).step(steps)
+                r2, u2 = sim.moments()
+            assert np.array_equal(r2, got[dtype][0]) and np.array_equal(u2, got[dtype][1]), dtype
+            _progress(capfd, f"full-horizon error: GPU {dtype} two-step kernel bit-identical")
     sim = oracle.Sim("D3Q19", (256, 256, 256), tau, mode="closed").init(rho, u)
     for t in range(every, steps + 1, every):
         sim.step(every)
