@@ -86,9 +86,13 @@ def timed_steps(sim, steps: int, warmup: int) -> float:
     return e0.elapsed_time(e1) / steps
 
 
-KERNEL_NAMES = {1: "scalar", 2: "row_wave", 3: "in_place", 4: "two_row", 5: "twist"}
+KERNEL_NAMES = {1: "scalar", 2: "row_wave", 3: "in_place", 4: "two_row", 5: "twist", 6: "two_step"}
 KERNEL_SYMBOLS = {"scalar": "k_step", "row_wave": "k_step_vec", "in_place": "k_step_ip", "two_row": "k_step_pair",
-                  "twist": "k_step_tw"}
+                  "twist": "k_step_tw", "two_step": "k_step2"}
+# time steps one launch of a kernel takes (the two-step kernel: two; per-launch
+# figures count both)
+STEPS_PER_LAUNCH = {"two_step": 2}
+STORAGE_CTYPE = {"fp64": "double", "fp32": "float", "fp16": "_Float16", "bf16": "bf16_t"}
 
 
 MAX_GRAPH_CHUNK = 4096
@@ -128,9 +132,11 @@ def measure_box(lattice, dims, tau, dtype, rho, u, steps, warmup, tune=True, **k
     nsites = info["nsites"]
     mlups = nsites / (ms * 1e-3) / 1e6
     gbs = bytes_site * nsites / (ms * 1e-3) / 1e9
+    kernel = KERNEL_NAMES[info["kernel"]]
     return {"value": mlups, "unit": "MLUPS", "ms_per_step": ms, "steps": steps,
             "bytes_per_site_update": bytes_site, "nsites": nsites, "achieved_GBs": gbs,
-            "roofline_frac": gbs / PEAK_HBM_GBS, "kernel": KERNEL_NAMES[info["kernel"]],
+            "roofline_frac": gbs / PEAK_HBM_GBS, "kernel": kernel,
+            "steps_per_launch": STEPS_PER_LAUNCH.get(kernel, 1),
             "block": info["block"], "grid": info["grid"], "conservation": conservation,
             "launches": {"graph_chunk": int(info["graph_chunk"]), "graph_launches": steps // int(info["graph_chunk"]),
                          "direct_launches": steps % int(info["graph_chunk"]), "warmup_direct_launches": warmup},
@@ -420,18 +426,20 @@ def main():
     ap.add_argument("--graph-chunk", type=int, default=None,
                     help="steps per captured graph (default min(steps, 4096); 1 = direct launches, as counter "
                          "collection needs)")
-    ap.add_argument("--kernel", choices=["tune", "scalar", "row_wave", "in_place", "two_row", "twist"],
+    ap.add_argument("--kernel", choices=["tune", "scalar", "row_wave", "in_place", "two_row", "twist", "two_step"],
                     default="tune",
                     help="headline step kernel: autotuned (default) or pinned")
     ap.add_argument("--block", type=int, default=256, help="threads per block when --kernel is pinned")
-    ap.add_argument("--dtype", choices=["fp32", "fp16", "bf16"], default="fp32",
+    ap.add_argument("--dtype", choices=["fp32", "fp16", "bf16", "fp64"], default="fp32",
                     help="storage type of the headline box or of --workload batch256 (fp32 is the headline; the others "
-                         "are profiling aids)")
+                         "are profiling aids; the batch takes fp32, fp16 or bf16)")
     ap.add_argument("--workload", choices=["turbulence256", "batch256", "d3q39_192"], default="turbulence256",
                     help="turbulence256: the headline box (default); batch256: only the 256-box FP32 batch; "
                          "d3q39_192: only the D3Q39 192^3 FP32 shear wave; the last two print their own roofline "
                          "(profiling aids)")
     args = ap.parse_args()
+    if args.workload == "batch256" and args.dtype == "fp64":
+        ap.error("--workload batch256 takes --dtype fp32, fp16 or bf16")
     global GRAPH_CHUNK
     if args.graph_chunk is not None:
         if not 1 <= args.graph_chunk <= MAX_GRAPH_CHUNK:
@@ -469,12 +477,18 @@ def main():
     log(f"headline: {head['value']:.0f} MLUPS with the {head['kernel']} step, block {head['block']}")
     nsites = head["nsites"]
     traffic, traffic_src = traffic_per_launch(head["kernel"], "turbulence256", hd)
+    spl = head["steps_per_launch"]
     roofline = {"bound": "hbm", "achieved": head["achieved_GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": head["achieved_GBs"] / PEAK_HBM_GBS, "traffic": traffic,
-                "algorithmic_bytes_per_launch": head["bytes_per_site_update"] * nsites,
-                "kernel": KERNEL_SYMBOLS[head["kernel"]] + "<D3Q19, "
-                          + {"fp32": "float", "fp16": "_Float16", "bf16": "bf16_t"}[hd] + ", K=3>",
-                "launch": {"kernel": head["kernel"], "block": head["block"]}, "traffic_source": traffic_src}
+                "algorithmic_bytes_per_launch": head["bytes_per_site_update"] * nsites * spl,
+                "steps_per_launch": spl,
+                "kernel": KERNEL_SYMBOLS[head["kernel"]] + "<D3Q19, " + STORAGE_CTYPE[hd] + ", K=3>",
+                "launch": {"kernel": head["kernel"], "block": head["block"], "grid": head["grid"]},
+                "traffic_source": traffic_src}
+    if spl == 2:
+        roofline["note"] = ("achieved counts 2*Q*S bytes per site update, one read and one write of every "
+                            "population per step; this kernel reads and writes the state once per two steps, "
+                            "so its HBM traffic (counters) is about half that and achieved can exceed a copy's rate")
 
     log("copy probe at the same footprint")
     copy_bytes = head["bytes_per_site_update"] // 2 * nsites
@@ -519,12 +533,14 @@ def main():
 
     # measured HBM traffic of the variants whose launch has a committed counter summary
     for name, wl, dt in [("fp16", "turbulence256", "fp16"), ("bf16", "turbulence256", "bf16"),
+                         ("fp64", "turbulence256", "fp64"),
                          ("batched_fp32", "batch256", "fp32"), ("batched_fp16", "batch256", "fp16"),
                          ("d3q39_fp32_192", "d3q39_192", "fp32")]:
         if name in variants:
             v = variants[name]
             tb, src = traffic_per_launch(v["kernel"], wl, dt)
-            v["traffic_over_algorithmic"] = tb / (v["bytes_per_site_update"] * v["nsites"]) if tb else None
+            alg = v["bytes_per_site_update"] * v["nsites"] * v["steps_per_launch"]
+            v["traffic_over_algorithmic"] = tb / alg if tb else None
             v["traffic_source"] = src
 
     galilean = None
