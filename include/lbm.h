@@ -215,7 +215,7 @@ lbm_status lbm_set_launch(lbm_t h, int32_t block, int32_t grid);
  * they handle the swapped one.
  * LBM_KERNEL_TWO_ROW needs a single box with ny even (else LBM_EINVAL).
  * LBM_KERNEL_TWO_STEP needs a single D3Q15 or D3Q19 box with nx a multiple of
- * 32, ny a multiple of 16 (8 for FP64 storage) and one z-plane of populations
+ * 64, ny a multiple of 8 (4 for FP64 storage) and one z-plane of populations
  * (Q nx ny values) below 2 GiB, else LBM_EINVAL.  An odd step count ends with
  * one step of the scalar kernel; the state stays in the natural layout.
  * May be called at any time: on an initialised handle the state is first

@@ -43,9 +43,12 @@ constexpr int kBlockSites = 64;                  // sites per block of a batched
 // two_step_tile_y(elem) sites of a z-plane per block, which also computes the
 // one-site ring around them in its first step.  8-byte storage takes half the
 // rows, so that the kernel's two LDS planes (2 Q (TX + 2)(TY + 2) values)
-// stay within a compute unit's 160 KiB.
-constexpr int kTwoStepTileX = 32;
-constexpr int two_step_tile_y(size_t elem) { return elem == 8 ? 8 : 16; }
+// stay within a compute unit's 160 KiB.  (Measured on D3Q19 256^3: 64 x 8
+// tiles ran 8.5% faster than 32 x 16 in FP32, and 64 x 4 9% faster than 32 x 8
+// in FP64: the ring costs more arithmetic, but each population row's ring
+// cache lines are shared by twice as many sites.)
+constexpr int kTwoStepTileX = 64;
+constexpr int two_step_tile_y(size_t elem) { return elem == 8 ? 4 : 8; }
 
 // Whether the two-step kernel applies to a single nx x ny x nz box: a 3-D
 // lattice whose velocity components are at most 1 in magnitude (a one-site

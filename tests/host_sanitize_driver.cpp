@@ -112,20 +112,20 @@ static void test_two_step_fits()
     const int64_t big = std::numeric_limits<int64_t>::max();
     for (int dtype = 0; dtype < 4; ++dtype) {
         EXPECT(two_step_fits(q19, dtype, 256, 256, 256));
-        EXPECT(two_step_fits(q15, dtype, 32, 16, 1));
+        EXPECT(two_step_fits(q15, dtype, 64, 8, 1));
         EXPECT(!two_step_fits(q9, dtype, 64, 64, 1));
         EXPECT(!two_step_fits(q39, dtype, 64, 64, 64));
-        EXPECT(!two_step_fits(q19, dtype, 48, 32, 4));   // nx not a multiple of 32
-        EXPECT(!two_step_fits(q19, dtype, 32, 12, 4));   // ny not a multiple of 8
+        EXPECT(!two_step_fits(q19, dtype, 96, 32, 4));   // nx not a multiple of 64
+        EXPECT(!two_step_fits(q19, dtype, 64, 6, 4));    // ny not a multiple of 4
         EXPECT(!two_step_fits(q19, dtype, 0, 16, 4));
-        EXPECT(!two_step_fits(q19, dtype, 32, 16, 0));
-        EXPECT(!two_step_fits(q19, dtype, -32, 16, 4));
+        EXPECT(!two_step_fits(q19, dtype, 64, 16, 0));
+        EXPECT(!two_step_fits(q19, dtype, -64, 16, 4));
         EXPECT(!two_step_fits(q19, dtype, big, big, big));
-        EXPECT(!two_step_fits(q19, dtype, 32, int64_t(1) << 40, 1));
+        EXPECT(!two_step_fits(q19, dtype, 64, int64_t(1) << 40, 1));
     }
-    EXPECT(two_step_fits(q19, 0, 32, 24, 3));    // FP64 tile: 32 x 8
-    EXPECT(!two_step_fits(q19, 1, 32, 24, 3));   // FP32 tile: 32 x 16
-    EXPECT(!two_step_fits(q19, 4, 32, 16, 3));   // unknown dtype
+    EXPECT(two_step_fits(q19, 0, 64, 12, 3));    // FP64 tile: 64 x 4
+    EXPECT(!two_step_fits(q19, 1, 64, 12, 3));   // FP32 tile: 64 x 8
+    EXPECT(!two_step_fits(q19, 4, 64, 16, 3));   // unknown dtype
     // one z-plane of populations must stay below 2 GiB: Q nx ny elem < 2^31
     EXPECT(two_step_fits(q19, 1, 8192, 3440, 1));    // 19 * 8192 * 3440 * 4 = 2141 MB < 2^31
     EXPECT(!two_step_fits(q19, 1, 8192, 3456, 1));   // 19 * 8192 * 3456 * 4 > 2^31

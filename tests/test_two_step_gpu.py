@@ -20,18 +20,18 @@ def _fields(dims, seed, amp=0.05):
     return 1.0 + rng.uniform(-0.01, 0.01, size=shape), rng.uniform(-amp, amp, size=(3,) + shape)
 
 
-# boxes of 1 x 1 to 3 x 4 columns (32 x 16 sites; 32 x 8 for FP64), nz from 1
+# boxes of 1 x 1 to 3 x 5 columns (64 x 8 sites; 64 x 4 for FP64), nz from 1
 CASES = [
-    ("D3Q19", (64, 32, 5), "fp32", {}),
-    ("D3Q19", (32, 16, 1), "fp32", {}),
-    ("D3Q19", (32, 16, 2), "fp32", {"K": 2}),
-    ("D3Q19", (96, 48, 7), "fp16", {"collision": "bgk"}),
-    ("D3Q19", (32, 32, 3), "bf16", {}),
-    ("D3Q19", (64, 16, 6), "fp64", {"theta": 0.5}),
-    ("D3Q19", (32, 8, 9), "fp64", {}),
+    ("D3Q19", (128, 16, 5), "fp32", {}),
+    ("D3Q19", (64, 8, 1), "fp32", {}),
+    ("D3Q19", (64, 8, 2), "fp32", {"K": 2}),
+    ("D3Q19", (192, 24, 7), "fp16", {"collision": "bgk"}),
+    ("D3Q19", (64, 32, 3), "bf16", {}),
+    ("D3Q19", (128, 12, 6), "fp64", {"theta": 0.5}),
+    ("D3Q19", (64, 4, 9), "fp64", {}),
     ("D3Q15", (64, 32, 4), "fp32", {}),
-    ("D3Q15", (32, 24, 3), "fp64", {"K": 2}),
-    ("D3Q15", (96, 64, 2), "fp16", {"theta": 0.3}),
+    ("D3Q15", (64, 20, 3), "fp64", {"K": 2}),
+    ("D3Q15", (192, 16, 2), "fp16", {"theta": 0.3}),
 ]
 
 
@@ -49,7 +49,7 @@ def test_two_step_any_grid(grid):
     """Blocks take runs of column-planes: a run may span columns (small
     grids), a grid not a multiple of 8 takes the plain block order, and blocks
     past the last column-plane stay idle."""
-    dims = (96, 32, 11)  # 6 columns x 11 planes = 66 column-planes
+    dims = (192, 16, 11)  # 6 columns x 11 planes = 66 column-planes
     rho, u = _fields(dims, seed=grid)
     a = run_gpu("D3Q19", dims, 0.57, "fp32", rho, u, 14, kernel="two_step", grid=grid)
     b = run_gpu("D3Q19", dims, 0.57, "fp32", rho, u, 14, kernel="scalar")
@@ -68,8 +68,8 @@ def test_two_step_graph_chunks(chunk):
 
 
 @pytest.mark.parametrize("lattice,dims,dtype", [("D2Q9", (64, 32, 1), "fp32"), ("D3Q39", (64, 32, 4), "fp32"),
-                                                ("D3Q19", (48, 32, 4), "fp32"), ("D3Q19", (64, 24, 4), "fp32"),
-                                                ("D3Q19", (64, 12, 4), "fp64"), ("D3Q15", (64, 8, 4), "fp16")])
+                                                ("D3Q19", (96, 32, 4), "fp32"), ("D3Q19", (64, 12, 4), "fp32"),
+                                                ("D3Q19", (64, 6, 4), "fp64"), ("D3Q15", (32, 8, 4), "fp16")])
 def test_two_step_fit_rules(lattice, dims, dtype):
     from paper_2002_02503_amd import lbm
 
@@ -77,15 +77,15 @@ def test_two_step_fit_rules(lattice, dims, dtype):
         lbm.Simulation(lattice, dims, 0.6, dtype=dtype, kernel="two_step")
     assert e.value.name == "LBM_EINVAL"
     with pytest.raises(lbm.LBMError) as e:
-        lbm.Simulation("D3Q19", [(32, 16, 4), (32, 16, 4)], [0.6, 0.7], kernel="two_step")
+        lbm.Simulation("D3Q19", [(64, 8, 4), (64, 8, 4)], [0.6, 0.7], kernel="two_step")
     assert e.value.name == "LBM_EINVAL"
 
 
 def test_two_step_fits_fp64_tile():
-    """ny a multiple of 8 but not 16 fits the FP64 tile only."""
+    """ny a multiple of 4 but not 8 fits the FP64 tile only."""
     from paper_2002_02503_amd import lbm
 
-    dims = (32, 24, 3)
+    dims = (64, 12, 3)
     rho, u = _fields(dims, seed=5)
     a = run_gpu("D3Q19", dims, 0.6, "fp64", rho, u, 6, kernel="two_step")
     b = run_gpu("D3Q19", dims, 0.6, "fp64", rho, u, 6, kernel="scalar")
@@ -137,7 +137,7 @@ def test_switching_to_and_from_two_step_mid_run():
 def test_two_step_checkpoint_resumes_in_any_kernel():
     from paper_2002_02503_amd import lbm
 
-    dims = (32, 16, 7)
+    dims = (64, 8, 7)
     rho, u = _fields(dims, seed=31)
     with lbm.Simulation("D3Q19", dims, 0.6, dtype="fp32", kernel="two_step") as a, \
             lbm.Simulation("D3Q19", dims, 0.6, dtype="fp32", kernel="scalar") as b:
