@@ -37,14 +37,14 @@ namespace lbm {
 // plain order with 64 x 8 tiles, 12% with 32 x 16 ones).
 // ---------------------------------------------------------------------------
 
-template <class S>
+template <class S, int KIND>
 constexpr int step2_threads()
 {
-    return (kTwoStepTileX + 2) * (two_step_tile_y(sizeof(S)) + 2);
+    return (kTwoStepTileX + 2) * (two_step_tile_y(sizeof(S), KIND == kFilteredQ) + 2);
 }
 
 template <class L, class S, int K, int KIND>
-__global__ __launch_bounds__(step2_threads<S>(), 2) void k_step2(const S* __restrict__ src, S* __restrict__ dst,
+__global__ __launch_bounds__((step2_threads<S, KIND>()), 2) void k_step2(const S* __restrict__ src, S* __restrict__ dst,
                                                                  Step2Geom geo, typename Store<S>::R omega,
                                                                  typename Store<S>::R theta)
 {
@@ -52,7 +52,7 @@ __global__ __launch_bounds__(step2_threads<S>(), 2) void k_step2(const S* __rest
     using R = typename ST::R;
     constexpr bool PROJ = !std::is_same<R, double>::value;
     constexpr int Q = L::Q;
-    constexpr int TX = kTwoStepTileX, TY = two_step_tile_y(sizeof(S));
+    constexpr int TX = kTwoStepTileX, TY = two_step_tile_y(sizeof(S), KIND == kFilteredQ);
     constexpr int WX = TX + 2, NT = WX * (TY + 2);
     static_assert(L::D == 3 && L::R == 1, "a one-site ring in x, y and z");
     static_assert((TX * TY) % 64 == 0, "step 2 on whole waves");
@@ -159,7 +159,7 @@ hipError_t launch_step2_l(int K, int kind, const void* src, void* dst, const Ste
             using R = typename Store<S>::R;
             constexpr int KK = decltype(Kc)::value;
             constexpr int KD = decltype(Kind)::value;
-            k_step2<L, S, KK, KD><<<dim3(unsigned(grid)), step2_threads<S>(), 0, s>>>(
+            k_step2<L, S, KK, KD><<<dim3(unsigned(grid)), step2_threads<S, KD>(), 0, s>>>(
                 static_cast<const S*>(src), static_cast<S*>(dst), geo, R(omega), R(theta));
             return hipGetLastError();
         });

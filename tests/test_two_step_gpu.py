@@ -25,6 +25,7 @@ CASES = [
     ("D3Q19", (128, 16, 5), "fp32", {}),
     ("D3Q19", (64, 8, 1), "fp32", {}),
     ("D3Q19", (64, 8, 2), "fp32", {"K": 2}),
+    ("D3Q19", (64, 16, 5), "fp32", {"theta": 0.5}),
     ("D3Q19", (192, 24, 7), "fp16", {"collision": "bgk"}),
     ("D3Q19", (64, 32, 3), "bf16", {}),
     ("D3Q19", (128, 12, 6), "fp64", {"theta": 0.5}),
