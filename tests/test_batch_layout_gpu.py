@@ -248,14 +248,16 @@ def test_size_limits_are_refused_before_allocation():
             assert sim.info()["nsites"] == dims[0] * dims[1] * dims[2]
 
 
-@pytest.mark.parametrize("kernel", ["in_place", "twist"])
+@pytest.mark.parametrize("kernel", ["in_place", "twist", "two_step"])
 def test_box_of_more_than_2_31_sites(kernel):
     """A single D3Q19 box of 2^31 + 2^20 sites (1024 x 1024 x 2049), FP16, in
-    place (82 GB of populations, fields on the device).  The field varies
-    along x and z (u_x along z, u_y along x), so a site index that wrapped at
-    32 bits would land on a site with other values: after the steps the field
-    is y-independent bit for bit and equals the 1024 x 1 x 2049 box's run, and
-    the FP64 totals are ny times that box's."""
+    place (82 GB of populations, fields on the device), or with the two-step
+    kernel (two buffers, 164 GB; its z-planes start past 4 GiB).  The field
+    varies along x and z (u_x along z, u_y along x), so a site index that
+    wrapped at 32 bits would land on a site with other values: after the steps
+    the field is y-independent bit for bit and equals the 1024 x 1 x 2049 box's
+    run (one-site step for the two-step case, whose tile needs ny >= 8), and the
+    FP64 totals are ny times that box's."""
     import torch
 
     from paper_2002_02503_amd import lbm
@@ -291,7 +293,8 @@ def test_box_of_more_than_2_31_sites(kernel):
     del r, uu
     torch.cuda.empty_cache()
     rho1, u1 = fields(1, False)
-    with lbm.Simulation("D3Q19", (nx, 1, nz), tau, dtype="fp16", kernel=kernel) as one:
+    with lbm.Simulation("D3Q19", (nx, 1, nz), tau, dtype="fp16",
+                        kernel="scalar" if kernel == "two_step" else kernel) as one:
         one.init(rho1, u1).step(steps)
         tot1 = one.totals()[0]
         r1, uu1 = one.moments()
