@@ -97,7 +97,8 @@ typedef struct {
     int64_t t;                   /* steps taken since lbm_init */
     int64_t bytes_per_site_update; /* 2 * Q * sizeof(storage): one read + one write per population */
     uint64_t state_bytes;        /* bytes of one population buffer (see lbm_state_bytes) */
-    int32_t block, grid;         /* launch shape in use (threads per block; batched grid size, 0 = one wave per tile) */
+    int32_t block, grid;         /* launch shape in use (threads per block; batched grid size, 0 = one wave per
+                                    tile; for LBM_KERNEL_TWO_STEP its number of blocks) */
     int32_t graph_chunk;         /* steps per captured graph */
     int32_t kernel;              /* step kernel in use (lbm_kernel, never AUTO) */
     int32_t collision;           /* lbm_collision in use */
