@@ -488,7 +488,7 @@ hipError_t launch_two(lbm_ctx* h, int parity, hipStream_t s)
     geo.ny = int(h->dims[1]);
     geo.nz = int(h->dims[2]);
     geo.ncx = int(h->dims[0] / kTwoStepTileX);
-    const long long ncy = h->dims[1] / two_step_tile_y(h->elem, step_kind(h) == kFilteredQ);
+    const long long ncy = h->dims[1] / two_step_tile_y(h->elem);
     geo.total = (long long)geo.ncx * ncy * geo.nz;
     const int grid = two_step_grid(h);
     geo.per = (geo.total + grid - 1) / grid;

@@ -47,11 +47,8 @@ constexpr int kBlockSites = 64;                  // sites per block of a batched
 // tiles ran 8.5% faster than 32 x 16 in FP32, and 64 x 4 9% faster than 32 x 8
 // in FP64: the ring costs more arithmetic, but each population row's ring
 // cache lines are shared by twice as many sites.)
-// The energy-flux collision kind needs more registers than the 8-row tile's
-// eleven waves per block leave (168 per lane), so it takes the 4-row tile too
-// (seven waves, 256 registers); a box that fits the 8-row tile fits that one.
 constexpr int kTwoStepTileX = 64;
-constexpr int two_step_tile_y(size_t elem, bool energy_flux = false) { return (elem == 8 || energy_flux) ? 4 : 8; }
+constexpr int two_step_tile_y(size_t elem) { return elem == 8 ? 4 : 8; }
 
 // Whether the two-step kernel applies to a single nx x ny x nz box: a 3-D
 // lattice whose velocity components are at most 1 in magnitude (a one-site
