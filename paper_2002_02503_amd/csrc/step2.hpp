@@ -27,8 +27,11 @@ namespace lbm {
 // adds (TX + 2)(TY + 2) / (TX TY) - 1 of one step's arithmetic, and two extra
 // step-1 planes per column segment.  Each site's arithmetic is k_step's on
 // the same values, so the launch gives the bits of two k_step launches.
-// The LDS planes are double-buffered: step 2 at plane p reads the buffer that
-// step 1 filled while step 1 at p + 1 fills the other, one barrier per plane.
+// The LDS planes are double-buffered: a wave that has finished step 2 at
+// plane p - 1 (reading plane p's buffer) goes on to fill the other buffer with
+// plane p + 1 while slower waves still read, so one barrier per plane
+// suffices (the barrier after plane p + 1's writes comes after every read of
+// plane p - 1's buffer, which plane p + 2 refills).
 // The loads of plane p + 1 are issued before plane p's collisions, so they
 // are in flight during both steps.
 // Blocks are dealt to the eight XCDs in turn; with the grid a multiple of 8
