@@ -501,7 +501,9 @@ def main():
     if spl == 2:
         roofline["note"] = ("achieved counts 2*Q*S bytes per site update, one read and one write of every "
                             "population per step; this kernel reads and writes the state once per two steps, "
-                            "so its HBM traffic (counters) is about half that and achieved can exceed a copy's rate")
+                            "so its HBM traffic (traffic, counters: one write and about 1.7 reads of the state "
+                            "per launch) is well below that and achieved can exceed a copy's rate; traffic_GBs "
+                            "is the bandwidth it draws")
 
     log("copy probe at the same footprint")
     copy_bytes = head["bytes_per_site_update"] // 2 * nsites
