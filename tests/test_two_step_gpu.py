@@ -167,3 +167,27 @@ def test_two_step_matches_the_oracle(dtype):
     eu, er = rel_u(uu, u_ref), rel_rho(r, r_ref)
     print(f"two-step D3Q19 {dims} {dtype} {steps} steps: u {eu:.2e} rho {er:.2e}", flush=True)
     assert eu < BOUND[dtype] and er < BOUND[dtype]
+
+
+@pytest.mark.parametrize("dims,fits", [((64, 16, 5), True), ((96, 6, 5), False)])
+def test_cached_two_step_choice(tmp_path, dims, fits):
+    """A tune-cache line naming the two-step kernel is taken for a box it
+    fits and replaced by the one-site step for one it does not (nx not a
+    multiple of 64, ny not of 8); either way the run gives the reference bits."""
+    from paper_2002_02503_amd import lbm
+
+    rho, u = _fields(dims, seed=17)
+    ref = run_gpu("D3Q19", dims, 0.6, "fp32", rho, u, 9, kernel="scalar")
+    cache = tmp_path / "tune.txt"
+    with lbm.Simulation("D3Q19", dims, 0.6, dtype="fp32") as sim:
+        sim.init(rho, u).tune(steps=2, cache=str(cache))
+    key = open(cache).read().splitlines()[-1].split(" | ")[0]
+    with open(cache, "a") as f:
+        f.write(key + f" | {lbm.KERNELS['two_step']} 0 0\n")
+    with lbm.Simulation("D3Q19", dims, 0.6, dtype="fp32") as sim:
+        sim.init(rho, u).tune(steps=2, cache=str(cache))
+        kernel = sim.info()["kernel"]
+        sim.step(9)
+        r, uu = sim.moments()
+    assert kernel == (lbm.KERNELS["two_step"] if fits else lbm.KERNELS["scalar"])
+    assert np.array_equal(r, ref[0]) and np.array_equal(uu, ref[1])
