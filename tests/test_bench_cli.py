@@ -56,3 +56,18 @@ def test_source_hash_covers_the_device_sources():
     assert "csrc/step.hpp" in names and "csrc/step_batch.hpp" in names and "csrc/collide.hpp" in names
     assert "build.py" in names and "csrc/api.hip" not in names
     assert len(bench.source_hash()) == 16
+
+
+def test_counted_traffic_rate_counts_every_step_of_a_launch():
+    """bench.counted_rate divides a launch's counted bytes by the time of one
+    launch: ms_per_step times the steps a launch takes (two for the two-step
+    kernel), so the rate does not double when a launch covers two steps."""
+    import bench
+
+    one = {"ms_per_step": 0.5, "steps_per_launch": 1}
+    two = {"ms_per_step": 0.25, "steps_per_launch": 2}
+    gbs1, frac1 = bench.counted_rate(one, 2.0e9)
+    gbs2, frac2 = bench.counted_rate(two, 2.0e9)
+    assert abs(gbs1 - 4000.0) < 1e-9 and abs(gbs2 - 4000.0) < 1e-9
+    assert abs(frac1 - 0.5) < 1e-12 and abs(frac2 - 0.5) < 1e-12
+    assert bench.counted_rate(one, None) == (None, None)
