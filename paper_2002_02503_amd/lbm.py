@@ -183,7 +183,10 @@ class Simulation:
     box), storage dtype ("fp64", "fp32", "fp16", "bf16"), optional Hermite
     order K, collision operator ("filtered" or "bgk") with the energy-flux
     weight theta (lbm_set_collision), launch shape (block, grid) and steps per
-    captured graph.
+    captured graph.  kernel picks the single-box step (lbm_set_kernel; a key of
+    KERNELS: "scalar", "row_wave", "in_place", "two_row", "twist" or
+    "two_step", the last taking two steps per launch); "auto" leaves the
+    choice to the library, and tune() to measurement.
     """
 
     def __init__(self, lattice: str, dims, tau, dtype: str = "fp32", K: int | None = None,
