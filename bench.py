@@ -5,7 +5,9 @@ Workload (the headline): D3Q19, 256^3 periodic box, tau = 0.51, decaying
 turbulence from a seeded random-phase field (k0 = 4, u_rms = 0.04), FP32
 storage; FP16 and BF16 storage of the deviations, the batched form (256 boxes)
 and D3Q39 (192^3) are reported beside it.  A "step" is one application of the
-lattice Boltzmann equation to every site.  Inputs are resident in HBM before
+lattice Boltzmann equation to every site; the two-step kernel, where the tuner
+picks it, takes two steps per launch, and per-launch figures (roofline bytes,
+counter traffic) then count both.  Inputs are resident in HBM before
 the timed region.  Each measurement sets the handle's graph chunk to
 min(K, 4096) and builds its step graphs beforehand, so the K timed steps are
 one captured-graph launch (K <= 4096); the W warm-up steps before them, fewer
