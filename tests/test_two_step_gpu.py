@@ -191,3 +191,27 @@ def test_cached_two_step_choice(tmp_path, dims, fits):
         r, uu = sim.moments()
     assert kernel == (lbm.KERNELS["two_step"] if fits else lbm.KERNELS["scalar"])
     assert np.array_equal(r, ref[0]) and np.array_equal(uu, ref[1])
+
+
+def _random_cases(n, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        dtype = ["fp32", "fp64", "fp16", "bf16"][rng.integers(4)]
+        ty = 4 if dtype == "fp64" else 8
+        lattice = ["D3Q19", "D3Q15"][rng.integers(2)]
+        dims = (64 * int(rng.integers(1, 4)), ty * int(rng.integers(1, 6)), int(rng.integers(1, 10)))
+        kw = [{}, {"collision": "bgk"}, {"K": 2}, {"theta": 0.4}][rng.integers(4)]
+        out.append((lattice, dims, dtype, kw, int(rng.integers(1, 24)), int(rng.choice([0, 1, 5, 8, 24, 4096]))))
+    return out
+
+
+@pytest.mark.parametrize("lattice,dims,dtype,kw,steps,grid", _random_cases(16, 2002))
+def test_two_step_random_shapes(lattice, dims, dtype, kw, steps, grid):
+    """Seeded random boxes (several columns, nz from 1), step counts, grids
+    (0: one block per compute unit), storage types and collision kinds: the
+    two-step kernel gives the one-site step's bits."""
+    rho, u = _fields(dims, seed=steps * 7 + sum(dims))
+    a = run_gpu(lattice, dims, 0.58, dtype, rho, u, steps, kernel="two_step", grid=grid, **kw)
+    b = run_gpu(lattice, dims, 0.58, dtype, rho, u, steps, kernel="scalar", **kw)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
