@@ -121,7 +121,9 @@ __global__ __launch_bounds__(step2_threads<S>(), 2) void k_step2(const S* __rest
             });
         };
 
-        R next[Q], hold0[Q], hold1a[Q], hold1b[Q];
+        // held LDS values: read from the first plane on, used from the third
+        // (k >= 2); zeroed so that no read is of an indeterminate value
+        R next[Q], hold0[Q] = {}, hold1a[Q] = {}, hold1b[Q] = {};
         const int planes = zb - za + 2;  // step-1 planes za - 1 .. zb
         pull(za - 1, next);
         for (int k = 0; k < planes; ++k) {
